@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark of the Aggregate Risk Analysis trial pass on one MI355X.
+
+Workload: the paper's experiment shape (Section IV) -- a YET of 1,000,000
+trials x 1,000 events over a 2,000,000-event catalogue and one layer of 16
+ELTs x 20,000 events (lognormal(10, 2) losses, per-ELT retention/limit at the
+10th/90th percentile, occurrence 1e5/1e7, aggregate 1e6/5e7), synthetic and
+seeded, resident in HBM before timing starts.
+
+One step = the trial pass of the layer over every trial (YLT written to HBM)
+plus PML/TVaR at 1-in-100 and 1-in-250 returned to the host.  Prints one JSON
+line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except Exception:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def time_layer(A, torch, yet, lay, ylt, steps, warmup, rps, with_pml=True):
+    """Wall time per step and mean kernel time (HIP events on the launch stream)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        A.run_layer(yet, lay, out=ylt)
+        if with_pml:
+            A.pml_tvar(ylt, rps)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    res = None
+    for i in range(steps):
+        evs[i][0].record(stream)
+        A.run_layer(yet, lay, out=ylt)
+        evs[i][1].record(stream)
+        if with_pml:
+            res = A.pml_tvar(ylt, rps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms = [a.elapsed_time(b) for a, b in evs]
+    return (t1 - t0) * 1e3 / steps, sum(k_ms) / len(k_ms), min(k_ms), res
+
+
+def cpu_baseline(wl, spec, target_s):
+    """The oracle on a bounded sample of the same workload, on the host cores."""
+    import numpy as np
+
+    from oracle import oracle
+    from paper_1412_4556_amd import workloads as W
+
+    threads = host_threads()
+    J = spec.n_elts
+
+    def run(n):
+        ids, off = W.yet_subset(wl.yet, np.arange(n))
+        t = time.perf_counter()
+        oracle.run_layer(ids, off, n, 0, wl.yet.catalog_size, spec, n_threads=threads)
+        return time.perf_counter() - t, int(off[-1])
+
+    probe = 2000 * threads
+    dt, ev = run(probe)
+    n = int(min(wl.yet.n_trials, max(probe, probe * target_s / max(dt, 1e-3))))
+    dt, ev = run(n)
+    return {"value": ev * J / dt, "unit": "lookups/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {wl.yet.n_trials} trials ({ev} trial-events x {J} ELTs), FP64, "
+                      f"OpenMP over trials, {dt:.1f} s incl. direct-table build",
+            "cpu_model": cpu_model(), "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
+    ap.add_argument("--layout", default="auto", choices=["auto", "direct", "sparse", "compact"])
+    ap.add_argument("--trials", type=int, default=1_000_000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(trials would shard by range across GPUs; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1412_4556_amd import ara as A
+    from paper_1412_4556_amd import workloads as W
+
+    wl = W.plain_paper(args.trials)
+    spec = wl.layers[0]
+    T, K, J = wl.yet.n_trials, wl.yet.fixed_len, spec.n_elts
+    log(f"generating YET {T} x {K} over {wl.yet.catalog_size} events")
+    ids, _ = W.yet_full(wl.yet)
+    t_ids = torch.from_numpy(ids).cuda()
+    del ids
+    yet = A.Yet(t_ids, None, T, wl.yet.catalog_size, K)
+    lay = A.Layer(yet, spec, args.precision, args.layout)
+    ylt = torch.empty(T, dtype=torch.float64, device="cuda")
+    rps = list(wl.return_periods)
+    log(f"layer: {J} ELTs, layout {lay.layout}, precision {lay.precision}, {lay.device_bytes} device bytes")
+
+    ms_step, k_ms, k_min, (pml, tvar) = time_layer(A, torch, yet, lay, ylt, args.steps, args.warmup, rps)
+    lookups = float(T) * K * J
+    algo_bytes = T * K * 4 + T * 8 + lay.device_bytes
+    achieved = algo_bytes / (k_ms * 1e-3) / 1e9
+    log(f"step {ms_step:.3f} ms, trial-pass kernel {k_ms:.3f} ms (min {k_min:.3f}), {achieved:.0f} GB/s")
+
+    extras = {}
+    if not args.no_extras:
+        for prec, layout, steps in (("fp32c", args.layout, args.steps), ("fp64", "direct", 3), ("fp32c", "direct", 3),
+                                    ("fp64", "sparse", 2), ("fp64", "compact", 3)):
+            if prec == args.precision and layout == args.layout:
+                continue
+            l2 = A.Layer(yet, spec, prec, layout)
+            s2, k2, _, _ = time_layer(A, torch, yet, l2, ylt, steps, 1, rps, with_pml=False)
+            extras[f"{prec}_{l2.layout}"] = {"kernel_ms": round(k2, 4), "lookups_per_s": lookups / (k2 * 1e-3),
+                                             "table_bytes": l2.device_bytes}
+            log(f"extra {prec}/{l2.layout}: kernel {k2:.3f} ms")
+            l2.close()
+        # per-event outputs (the cumulative-sum scan), FP64
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        A.run_layer_events(yet, lay, want_cum=False, want_net=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        out = A.run_layer_events(yet, lay, want_cum=False, want_net=True)
+        ev1.record()
+        torch.cuda.synchronize()
+        extras["per_event_net_output"] = {"kernel_ms": round(ev0.elapsed_time(ev1), 4)}
+        del out
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            A.pml_tvar(ylt, rps)
+        extras["pml_tvar_ms"] = round((time.perf_counter() - t) * 200, 4)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(wl, spec, args.cpu_seconds)
+        log(f"cpu baseline {cpu['value']:.3e} lookups/s on {cpu['cores']} threads")
+
+    rec = {
+        "metric": "trial-events x ELT lookups/sec",
+        "value": lookups / (ms_step * 1e-3),
+        "unit": "lookups/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f32c-scan+f64-aggregate",
+        "data": "synthetic (seeded; the paper's YET/ELT shapes, its data are not public)",
+        "config": {"workload": wl.name, "n_trials": T, "events_per_trial": K, "catalog": wl.yet.catalog_size,
+                   "elts": J, "elt_size": 20_000, "layout": lay.layout, "precision": lay.precision,
+                   "return_periods": rps},
+        "trial_events_per_s": T * K / (ms_step * 1e-3),
+        "kernel_ms": k_ms,
+        "hbm_gbps_algorithmic": achieved,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBPS, "traffic": None,
+                     "kernel": "k_trial_pass", "algorithmic_bytes": algo_bytes},
+        "cpu_baseline": cpu,
+        "pml": pml.tolist(),
+        "tvar": tvar.tolist(),
+        "device": torch.cuda.get_device_name(0),
+        "extras": extras,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

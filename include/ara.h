@@ -1,0 +1,185 @@
+/*
+ * ara.h -- C ABI of the MI355X (gfx950) Aggregate Risk Analysis trial pass.
+ *
+ * The operation is the per-layer, per-trial simulation of Varghese & Barker,
+ * "Are Clouds Ready to Accelerate Ad hoc Financial Simulations?", Section III
+ * (the YET / ELT / Layer data model, Algorithm 1 and its four steps):
+ *
+ *   for every trial i of the Year Event Table (YET), for every event E of the
+ *   trial in stored (time) order:
+ *     l_j  = loss of E in ELT j of the layer, 0 if E is not in ELT j
+ *     x_j  = min(max(l_j - r_j, 0), u_j)             per-ELT terms FT1
+ *     e    = x_0 + x_1 + ... + x_{J-1}                combined event loss
+ *     o    = min(max(e - FT2_1, 0), FT2_2)            occurrence terms FT2
+ *     S   += o                                        cumulative loss of the trial
+ *   YLT[i] = min(max(S - FT3_1, 0), FT3_2)            aggregate terms FT3
+ *
+ * Risk metrics read from the YLT (the paper names them without a formula):
+ * for a return period of N years over T trials, k = floor(T / N) >= 1,
+ * PML_N is the k-th largest year loss and TVaR_N the mean of the k largest.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns ara_status: ARA_OK (0) or a negative error code.
+ *     Nothing throws across this boundary.  ara_last_error() returns a
+ *     message for the last failing call on the calling thread.
+ *   - "d_" pointers are device pointers (HIP device memory of the current
+ *     device); "h_" pointers are host pointers.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     Launches are asynchronous on that stream unless stated otherwise.
+ *   - All floating-point outputs are IEEE binary64.
+ */
+#ifndef ARA_H
+#define ARA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ara_status;
+
+#define ARA_OK 0
+#define ARA_ERR_INVALID_ARG -1  /* null handle/pointer, bad size, bad enum */
+#define ARA_ERR_EVENT_RANGE -2  /* an event ID outside [0, catalog_size) */
+#define ARA_ERR_DUP_EVENT -3    /* the same event ID twice in one ELT (an ELT is a dictionary) */
+#define ARA_ERR_VALUE -4        /* NaN, negative loss or term, or infinite retention/loss */
+#define ARA_ERR_OOM -5          /* device or host allocation failed; no state was changed */
+#define ARA_ERR_DEVICE -6       /* a HIP call failed */
+#define ARA_ERR_RP -7           /* a return period leaves no tail trial (floor(T/N) < 1) */
+#define ARA_ERR_UNSUPPORTED -8  /* a valid request this build does not handle (e.g. too many ELTs) */
+
+#define ARA_MAX_ELTS 32         /* ELTs per layer; the paper's layers cover 3 to 30 */
+
+typedef struct ara_yet_s *ara_yet;
+typedef struct ara_layer_s *ara_layer;
+
+/* Arithmetic of the trial pass.
+ *   ARA_FP64  : losses, terms and sums in binary64.
+ *   ARA_FP32C : losses and per-ELT / occurrence terms stored and applied in
+ *               binary32; the cross-ELT sum and the per-trial cumulative sum
+ *               are compensated binary32 (TwoSum pairs); the aggregate terms
+ *               and the YLT are binary64.  (Section IV's single-precision
+ *               optimisation, with compensated accumulation added.) */
+typedef enum { ARA_FP64 = 0, ARA_FP32C = 1 } ara_precision;
+
+/* Device layout of a layer's ELTs (Section IV discusses direct-access versus
+ * compact tables).
+ *   ARA_LAYOUT_DIRECT  : one dense catalogue-sized table per ELT, ELT-major
+ *                        ([J][catalog]); J loads per event (the paper's choice).
+ *   ARA_LAYOUT_SPARSE  : per-ELT event IDs sorted ascending with their losses;
+ *                        a binary search per ELT per event.
+ *   ARA_LAYOUT_COMPACT : a presence bitmap over the catalogue with per-word
+ *                        ranks, and one row of J losses per event present in
+ *                        any ELT of the layer (event-major).
+ *   ARA_LAYOUT_AUTO    : the library's choice (currently COMPACT).
+ * Every layout gives bitwise the same YLT for the same precision. */
+typedef enum {
+    ARA_LAYOUT_AUTO = 0,
+    ARA_LAYOUT_DIRECT = 1,
+    ARA_LAYOUT_SPARSE = 2,
+    ARA_LAYOUT_COMPACT = 3
+} ara_layout;
+
+/* Register a device-resident YET (Section III: trials of event IDs ordered by
+ * time stamp; the time stamps themselves are not needed, only the order).
+ *   d_event_ids     int32 [n_events], BORROWED: must stay valid and unchanged
+ *                   until ara_destroy_yet.  16-byte alignment is faster but
+ *                   not required.
+ *   d_offsets       int64 [n_trials + 1] trial boundaries, d_offsets[0] == 0,
+ *                   non-decreasing; trial i is d_event_ids[off[i] .. off[i+1]).
+ *                   BORROWED like the IDs.  NULL means every trial holds
+ *                   events_per_trial events (n_events = n_trials * events_per_trial).
+ *   catalog_size    number of possible event IDs (1 .. 2^31-1).
+ * Validates (one device pass, synchronous on hip_stream) that every ID lies in
+ * [0, catalog_size) -> ARA_ERR_EVENT_RANGE, and that offsets are well formed
+ * -> ARA_ERR_INVALID_ARG.  On success *out receives a handle owned by the
+ * caller (free with ara_destroy_yet). */
+ara_status ara_create_yet(const int32_t *d_event_ids, const int64_t *d_offsets, int64_t n_trials,
+                          int64_t events_per_trial, int32_t catalog_size, void *hip_stream, ara_yet *out);
+
+/* Build one layer (Section III: a set of ELTs with their FT1 terms, plus the
+ * occurrence terms FT2 and aggregate terms FT3) in device memory.
+ *   n_elts          1 .. ARA_MAX_ELTS, the ELTs in layer order (the order of
+ *                   the cross-ELT sum).
+ *   h_elt_ids       int32, all ELTs' event IDs concatenated in layer order;
+ *                   ELT j has h_elt_sizes[j] entries (0 allowed), each in
+ *                   [0, catalog_size) of the YET and unique within the ELT.
+ *   h_elt_losses    binary64 losses, same layout; finite and >= 0.
+ *   h_ret, h_lim    FT1 per ELT: retention (finite, >= 0) and limit (>= 0,
+ *                   +INFINITY for none).
+ *   occ_ret/occ_lim FT2 occurrence retention (finite, >= 0) / limit (>= 0 or +INF).
+ *   agg_ret/agg_lim FT3 aggregate retention (finite, >= 0) / limit (>= 0 or +INF).
+ *   precision       ara_precision; layout: ara_layout.
+ * All host inputs are COPIED; the caller may free them on return.  Device
+ * memory is owned by the layer until ara_destroy_layer.  Synchronous.
+ * Errors: ARA_ERR_INVALID_ARG, ARA_ERR_EVENT_RANGE, ARA_ERR_DUP_EVENT,
+ * ARA_ERR_VALUE, ARA_ERR_UNSUPPORTED (n_elts > ARA_MAX_ELTS), ARA_ERR_OOM. */
+ara_status ara_create_layer(ara_yet yet, int32_t n_elts, const int32_t *h_elt_ids, const double *h_elt_losses,
+                            const int64_t *h_elt_sizes, const double *h_ret, const double *h_lim,
+                            double occ_ret, double occ_lim, double agg_ret, double agg_lim,
+                            int32_t precision, int32_t layout, ara_layer *out);
+
+/* The trial pass of one layer over the whole YET (Algorithm 1 for one
+ * layer): writes d_ylt[i] for every trial i.
+ *   d_ylt   binary64 [n_trials], caller-owned device memory.
+ * Asynchronous on hip_stream.  The result is deterministic: the same inputs
+ * give bitwise the same YLT on every call. */
+ara_status ara_run_layer(ara_yet yet, ara_layer layer, double *d_ylt, void *hip_stream);
+
+/* The trial pass with per-event outputs (Section III: aggregate terms act on
+ * the cumulative sum of occurrence losses, so the share of each occurrence in
+ * the aggregate-net loss depends on the events before it).
+ *   d_ylt        binary64 [n_trials] as in ara_run_layer (required).
+ *   d_event_cum  binary64 [n_events] or NULL: S_k, the cumulative occurrence
+ *                loss of the trial up to and including event k.
+ *   d_event_net  binary64 [n_events] or NULL: A_k - A_{k-1} with
+ *                A_k = min(max(S_k - FT3_1, 0), FT3_2), A_0 = 0; the
+ *                increments of a trial add up to its year loss.
+ * Per-event arrays are indexed like the YET's event IDs.  Asynchronous. */
+ara_status ara_run_layer_events(ara_yet yet, ara_layer layer, double *d_ylt, double *d_event_cum,
+                                double *d_event_net, void *hip_stream);
+
+/* Several layers over one YET in one launch (Algorithm 1's loop over the
+ * layers of a program): d_ylts[l] receives layer l's YLT (binary64
+ * [n_trials], caller-owned).  Each layer's YLT is bitwise the one
+ * ara_run_layer gives for it.  Asynchronous. */
+ara_status ara_run_layers(ara_yet yet, const ara_layer *layers, double *const *d_ylts, int32_t n_layers,
+                          void *hip_stream);
+
+/* PML and TVaR of a YLT for n_rp return periods (years, > 0).
+ *   d_ylt              binary64 [n_trials] device memory, n_trials in 1 .. 2^31-1,
+ *                      no NaN (-> ARA_ERR_VALUE).
+ *   h_return_periods   host [n_rp], 1 <= n_rp <= 16.
+ *   h_pml, h_tvar      host [n_rp] outputs.
+ * k = floor(n_trials / N) must be >= 1 (else ARA_ERR_RP).  PML is exactly the
+ * k-th largest entry; TVaR is the binary64 mean of the k largest entries.
+ * SYNCHRONOUS: returns once the results are on the host. */
+ara_status ara_pml_tvar(const double *d_ylt, int64_t n_trials, const double *h_return_periods, int32_t n_rp,
+                        double *h_pml, double *h_tvar, void *hip_stream);
+
+/* Device bytes a layer holds (for memory admission). */
+size_t ara_layer_device_bytes(ara_layer layer);
+
+/* Layout a layer was built with (after resolving ARA_LAYOUT_AUTO), its
+ * precision and its ELT count, or -1 for a NULL handle. */
+int32_t ara_layer_layout(ara_layer layer);
+int32_t ara_layer_precision(ara_layer layer);
+int32_t ara_layer_n_elts(ara_layer layer);
+
+/* Free a handle (NULL is ignored).  Waits for the device to finish any work
+ * that may still use it.  A YET must outlive the layers run against it. */
+void ara_destroy_layer(ara_layer layer);
+void ara_destroy_yet(ara_yet yet);
+
+/* Message of the last non-OK status returned on the calling thread. */
+const char *ara_last_error(void);
+
+/* ABI version of this header: 1. */
+int32_t ara_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARA_H */

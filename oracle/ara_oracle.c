@@ -25,7 +25,8 @@
  *   empty trial has year loss 0.  The optional per-event output is the
  *   increment of A that each occurrence causes, A_k - A_{k-1} with A_0 = 0:
  *   the part of the aggregate-net loss attributed to the k-th event, which
- *   is the quantity that depends on the order of prior events.
+ *   is the quantity that depends on the order of prior events; the other
+ *   optional per-event output is S itself after each event.
  *
  * Readings of points the paper leaves open are listed in the design notes:
  * the max(., 0) missing an argument in the printed FT2/FT3 formulas, the
@@ -69,6 +70,7 @@ int oracle_run_layer(const int32_t *event_ids,      /* [n_events] */
                      double *ylt,                   /* [n_trials] year losses */
                      double *occ_sum,               /* [n_trials] S before FT3, or NULL */
                      double *gross,                 /* [n_trials] sum of looked-up losses, or NULL */
+                     double *event_cum,             /* [n_events] S after event k, or NULL */
                      double *event_net)             /* [n_events] A_k - A_{k-1}, or NULL */
 {
     if (n_trials < 0 || n_elts < 0 || catalog_size < 0) return -1;
@@ -119,6 +121,7 @@ int oracle_run_layer(const int32_t *event_ids,      /* [n_events] */
             double o = clamp_excess(e, occ_ret, occ_lim);
             /* step 4: cumulative sum within the trial, aggregate terms */
             S += o;
+            if (event_cum) event_cum[k] = S;
             if (event_net) {
                 double A = clamp_excess(S, agg_ret, agg_lim);
                 event_net[k] = A - A_prev;

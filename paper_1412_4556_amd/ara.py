@@ -1,0 +1,175 @@
+"""Python interface of libara: the same operations as the C ABI, on torch
+tensors that live in HIP device memory.
+
+torch only supplies device memory and the current stream; every step of the
+trial pass runs in the HIP kernels of libara.so.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PRECISIONS = {"fp64": L.ARA_FP64, "fp32c": L.ARA_FP32C}
+LAYOUTS = {"auto": L.ARA_LAYOUT_AUTO, "direct": L.ARA_LAYOUT_DIRECT, "sparse": L.ARA_LAYOUT_SPARSE,
+           "compact": L.ARA_LAYOUT_COMPACT}
+LAYOUT_NAMES = {v: k for k, v in LAYOUTS.items()}
+
+
+def _stream(stream: Optional[torch.cuda.Stream] = None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _vp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Yet:
+    """A device-resident Year Event Table (borrows the given tensors)."""
+
+    def __init__(self, event_ids: torch.Tensor, offsets: Optional[torch.Tensor], n_trials: int,
+                 catalog_size: int, events_per_trial: int = 0, stream=None):
+        if event_ids.dtype != torch.int32 or not event_ids.is_cuda or not event_ids.is_contiguous():
+            raise ValueError("event_ids must be a contiguous int32 device tensor")
+        if offsets is not None and (offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous()):
+            raise ValueError("offsets must be a contiguous int64 device tensor")
+        self.event_ids = event_ids
+        self.offsets = offsets
+        self.n_trials = int(n_trials)
+        self.catalog_size = int(catalog_size)
+        self.events_per_trial = int(events_per_trial)
+        self.n_events = int(event_ids.numel())
+        h = ctypes.c_void_p()
+        L.check(L.lib().ara_create_yet(ctypes.c_void_p(event_ids.data_ptr()),
+                                       ctypes.c_void_p(offsets.data_ptr()) if offsets is not None else None,
+                                       self.n_trials, self.events_per_trial, self.catalog_size,
+                                       ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().ara_destroy_yet(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Layer:
+    """A layer's ELTs and terms, copied into library-owned device memory."""
+
+    def __init__(self, yet: Yet, spec, precision: str = "fp64", layout: str = "auto"):
+        ids, losses, sizes = spec.concat()
+        ids, losses, sizes = _np(ids, np.int32), _np(losses, np.float64), _np(sizes, np.int64)
+        ret, lim = _np(spec.ret, np.float64), _np(spec.lim, np.float64)
+        h = ctypes.c_void_p()
+        L.check(L.lib().ara_create_layer(yet.handle, int(spec.n_elts), _vp(ids), _vp(losses), _vp(sizes), _vp(ret),
+                                         _vp(lim), float(spec.occ_ret), float(spec.occ_lim), float(spec.agg_ret),
+                                         float(spec.agg_lim), PRECISIONS[precision], LAYOUTS[layout],
+                                         ctypes.byref(h)))
+        self._h = h
+        self.yet = yet
+        self.spec = spec
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def device_bytes(self) -> int:
+        return int(L.lib().ara_layer_device_bytes(self._h))
+
+    @property
+    def layout(self) -> str:
+        return LAYOUT_NAMES[int(L.lib().ara_layer_layout(self._h))]
+
+    @property
+    def precision(self) -> str:
+        return {0: "fp64", 1: "fp32c"}[int(L.lib().ara_layer_precision(self._h))]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().ara_destroy_layer(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_out(t: torch.Tensor, n: int, name: str):
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"{name} must be a contiguous float64 device tensor of >= {n} elements")
+
+
+def run_layer(yet: Yet, layer: Layer, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """YLT of one layer (float64 [n_trials]); asynchronous on the stream."""
+    if out is None:
+        out = torch.empty(yet.n_trials, dtype=torch.float64, device=yet.event_ids.device)
+    _check_out(out, yet.n_trials, "out")
+    L.check(L.lib().ara_run_layer(yet.handle, layer.handle, ctypes.c_void_p(out.data_ptr()),
+                                  ctypes.c_void_p(_stream(stream))))
+    return out
+
+
+def run_layer_events(yet: Yet, layer: Layer, want_cum: bool = True, want_net: bool = True, stream=None):
+    """(ylt, event_cum or None, event_net or None)."""
+    dev = yet.event_ids.device
+    ylt = torch.empty(yet.n_trials, dtype=torch.float64, device=dev)
+    cum = torch.empty(yet.n_events, dtype=torch.float64, device=dev) if want_cum else None
+    net = torch.empty(yet.n_events, dtype=torch.float64, device=dev) if want_net else None
+    L.check(L.lib().ara_run_layer_events(yet.handle, layer.handle, ctypes.c_void_p(ylt.data_ptr()),
+                                         ctypes.c_void_p(cum.data_ptr()) if cum is not None else None,
+                                         ctypes.c_void_p(net.data_ptr()) if net is not None else None,
+                                         ctypes.c_void_p(_stream(stream))))
+    return ylt, cum, net
+
+
+def run_layers(yet: Yet, layers: Sequence[Layer], outs: Optional[Sequence[torch.Tensor]] = None, stream=None):
+    """YLTs of several layers in one launch."""
+    n = len(layers)
+    if outs is None:
+        outs = [torch.empty(yet.n_trials, dtype=torch.float64, device=yet.event_ids.device) for _ in range(n)]
+    for o in outs:
+        _check_out(o, yet.n_trials, "outs[i]")
+    hs = (ctypes.c_void_p * n)(*[l.handle.value for l in layers])
+    ps = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    L.check(L.lib().ara_run_layers(yet.handle, hs, ps, n, ctypes.c_void_p(_stream(stream))))
+    return list(outs)
+
+
+def pml_tvar(ylt: torch.Tensor, return_periods: Sequence[float], stream=None):
+    """(pml, tvar) numpy arrays for the return periods; synchronous."""
+    _check_out(ylt, ylt.numel(), "ylt")
+    rp = _np(list(return_periods), np.float64)
+    pml = np.zeros(len(rp))
+    tvar = np.zeros(len(rp))
+    L.check(L.lib().ara_pml_tvar(ctypes.c_void_p(ylt.data_ptr()), int(ylt.numel()), _vp(rp), len(rp), _vp(pml),
+                                 _vp(tvar), ctypes.c_void_p(_stream(stream))))
+    return pml, tvar
+
+
+def yet_from_numpy(ids: np.ndarray, offsets: Optional[np.ndarray], n_trials: int, catalog_size: int,
+                   events_per_trial: int = 0, device: str = "cuda") -> Yet:
+    """Copy a host YET to the device and register it."""
+    t_ids = torch.from_numpy(np.ascontiguousarray(ids, np.int32)).to(device)
+    t_off = None if offsets is None else torch.from_numpy(np.ascontiguousarray(offsets, np.int64)).to(device)
+    return Yet(t_ids, t_off, n_trials, catalog_size, events_per_trial)

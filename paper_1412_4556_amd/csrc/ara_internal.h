@@ -1,0 +1,81 @@
+// Internal types shared by the host side of libara and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/ara.h"
+
+namespace ara {
+
+constexpr int kMaxElts = ARA_MAX_ELTS;
+constexpr int kWave = 64;
+
+// A device-resident YET as the kernels see it.
+struct YetView {
+    const int32_t *ids;      // [n_events]
+    const int64_t *offsets;  // [n_trials + 1] or nullptr (fixed length)
+    int64_t n_trials;
+    int64_t events_per_trial;  // used when offsets == nullptr
+    int64_t n_events;
+    int32_t aligned16;  // ids pointer is 16-byte aligned (vector loads allowed)
+};
+
+// Per-layer terms, in the arithmetic of the pass (T = double or float).
+template <typename T>
+struct Terms {
+    T ret[kMaxElts];
+    T lim[kMaxElts];
+    T occ_ret, occ_lim;
+    double agg_ret, agg_lim;  // aggregate terms are always binary64
+    int32_t n_elts;
+};
+
+// Device pointers of a layer's tables (only those of its layout are set).
+struct TablesView {
+    // DIRECT: [n_elts][catalog] losses
+    const void *direct;
+    // SPARSE: ELT j holds sp_ids/sp_loss[sp_off[j] .. sp_off[j+1]), ids ascending
+    const int32_t *sp_ids;
+    const void *sp_loss;
+    const int64_t *sp_off;
+    // COMPACT: bm[w] = {presence bits of events 32w..32w+31, number of present
+    // events below 32w}; rows[rank][n_elts] losses of present events
+    const uint2 *bm;
+    const void *rows;
+    int32_t catalog;
+    int32_t n_words;
+};
+
+enum Layout : int32_t { kDirect = ARA_LAYOUT_DIRECT, kSparse = ARA_LAYOUT_SPARSE, kCompact = ARA_LAYOUT_COMPACT };
+
+struct LayerHost {
+    int32_t n_elts = 0;
+    int32_t catalog = 0;
+    int32_t precision = 0;
+    int32_t layout = 0;
+    Terms<double> t64{};
+    Terms<float> t32{};
+    TablesView tab{};
+    int64_t n_present = 0;  // COMPACT: events present in at least one ELT
+    size_t bytes = 0;
+    // device allocations owned by the layer
+    void *alloc[6] = {};
+};
+
+// Launchers (ara_kernels.hip).  Return a hipError_t.
+hipError_t launch_validate_yet(const YetView &y, int32_t catalog, int32_t *d_flags, hipStream_t s);
+hipError_t launch_trial_pass(const YetView &y, const LayerHost &L, double *d_ylt, hipStream_t s);
+hipError_t launch_trial_pass_events(const YetView &y, const LayerHost &L, double *d_ylt, double *d_cum,
+                                    double *d_net, hipStream_t s);
+hipError_t launch_trial_pass_multi(const YetView &y, const LayerHost *const *layers, double *const *ylts,
+                                   int32_t n_layers, hipStream_t s, void *d_scratch, size_t scratch_bytes);
+size_t multi_scratch_bytes(int32_t n_layers);
+
+// Selection (ara_select.hip): PML / TVaR for n_rp tail sizes k[r].
+hipError_t pml_tvar_device(const double *d_ylt, int64_t n, const int64_t *h_k, int32_t n_rp, double *h_pml,
+                           double *h_tvar, int32_t *h_nan, hipStream_t s);
+
+}  // namespace ara

@@ -1,0 +1,403 @@
+// HIP kernels of the trial pass for gfx950 (CDNA4, wave64).
+//
+// Mapping: one wavefront owns one trial at a time (grid-stride over trials).
+// Lane l of the wave takes events [c + 4l, c + 4l + 4) of each 256-event
+// chunk c of the trial, read with one 16-byte load per lane, so a wave's
+// loads of the Year Event Table are fully coalesced.  Each lane turns its
+// events into occurrence losses (lookup, FT1, cross-ELT sum, FT2; Section
+// III steps 1-3) and keeps a private running sum; the trial total is a wave
+// reduction, and the aggregate terms FT3 (step 4) are applied in binary64.
+//
+// The per-event variant replaces the private sums by an inclusive scan over
+// the wave (DPP row shifts and row broadcasts) with a carry between chunks,
+// which yields the cumulative loss S_k after every event.
+#include "ara_internal.h"
+
+namespace ara {
+namespace {
+
+// --------------------------------------------------------------------------------------------
+// arithmetic
+template <typename T>
+__device__ __forceinline__ T clamp_excess(T x, T r, T u) {
+    // min(max(x - r, 0), u)
+    T v = x - r;
+    v = v < T(0) ? T(0) : v;
+    return v > u ? u : v;
+}
+
+// Knuth's TwoSum: s + err == a + b exactly (round-to-nearest, no overflow).
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &err) {
+    s = a + b;
+    float bb = s - a;
+    err = (a - (s - bb)) + (b - bb);
+}
+
+// Running sums.  Acc<double> is plain binary64; Acc<float> is a compensated
+// binary32 pair (sum, accumulated TwoSum errors).
+template <typename T>
+struct Acc;
+
+template <>
+struct Acc<double> {
+    double s;
+    __device__ __forceinline__ static Acc zero() { return Acc{0.0}; }
+    __device__ __forceinline__ void add(double o) { s += o; }
+    __device__ __forceinline__ static Acc combine(const Acc &a, const Acc &b) { return Acc{a.s + b.s}; }
+    __device__ __forceinline__ double value() const { return s; }
+};
+
+template <>
+struct Acc<float> {
+    float s, c;
+    __device__ __forceinline__ static Acc zero() { return Acc{0.0f, 0.0f}; }
+    __device__ __forceinline__ void add(float o) {
+        float t;
+        two_sum(s, o, s, t);
+        c += t;
+    }
+    __device__ __forceinline__ static Acc combine(const Acc &a, const Acc &b) {
+        Acc r;
+        float t;
+        two_sum(a.s, b.s, r.s, t);
+        r.c = (a.c + b.c) + t;
+        return r;
+    }
+    __device__ __forceinline__ double value() const { return (double)s + (double)c; }
+};
+
+// Combined event loss over the ELTs of a layer, in layer order.
+template <typename T>
+struct EventSum;
+
+template <>
+struct EventSum<double> {
+    double e = 0.0;
+    __device__ __forceinline__ void add(double x) { e += x; }
+    __device__ __forceinline__ double value() const { return e; }
+};
+
+template <>
+struct EventSum<float> {
+    float hi = 0.0f, lo = 0.0f;
+    __device__ __forceinline__ void add(float x) {
+        float t;
+        two_sum(hi, x, hi, t);
+        lo += t;
+    }
+    __device__ __forceinline__ float value() const { return hi + lo; }
+};
+
+// --------------------------------------------------------------------------------------------
+// cross-lane moves
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_i(int v) {
+    // lanes of rows outside ROW_MASK, and lanes whose source is outside the
+    // row, receive 0
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, true);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ Acc<double> dpp_acc(const Acc<double> &a) {
+    long long b = __double_as_longlong(a.s);
+    int lo = dpp_i<CTRL, ROW_MASK>((int)(b & 0xffffffffLL));
+    int hi = dpp_i<CTRL, ROW_MASK>((int)(b >> 32));
+    long long r = ((long long)(unsigned)lo) | ((long long)hi << 32);
+    return Acc<double>{__longlong_as_double(r)};
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ Acc<float> dpp_acc(const Acc<float> &a) {
+    return Acc<float>{__int_as_float(dpp_i<CTRL, ROW_MASK>(__float_as_int(a.s))),
+                      __int_as_float(dpp_i<CTRL, ROW_MASK>(__float_as_int(a.c)))};
+}
+
+// DPP controls (GFX9 encoding)
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+// Inclusive scan of a over the 64 lanes: shifts by 1, 2, 4, 8 inside each
+// 16-lane row, then row 0's total into row 1 and row 2's into row 3, then the
+// total of rows 0-1 into rows 2-3.  The combine order is fixed, so the result
+// is deterministic.
+template <typename T>
+__device__ __forceinline__ Acc<T> wave_inclusive_scan(Acc<T> a) {
+    a = Acc<T>::combine(dpp_acc<kRowShr1, 0xf>(a), a);
+    a = Acc<T>::combine(dpp_acc<kRowShr2, 0xf>(a), a);
+    a = Acc<T>::combine(dpp_acc<kRowShr4, 0xf>(a), a);
+    a = Acc<T>::combine(dpp_acc<kRowShr8, 0xf>(a), a);
+    a = Acc<T>::combine(dpp_acc<kRowBcast15, 0xa>(a), a);
+    a = Acc<T>::combine(dpp_acc<kRowBcast31, 0xc>(a), a);
+    return a;
+}
+
+__device__ __forceinline__ Acc<double> shfl_acc(const Acc<double> &a, int src) {
+    return Acc<double>{__shfl(a.s, src)};
+}
+__device__ __forceinline__ Acc<float> shfl_acc(const Acc<float> &a, int src) {
+    return Acc<float>{__shfl(a.s, src), __shfl(a.c, src)};
+}
+__device__ __forceinline__ Acc<double> shfl_xor_acc(const Acc<double> &a, int m) {
+    return Acc<double>{__shfl_xor(a.s, m)};
+}
+__device__ __forceinline__ Acc<float> shfl_xor_acc(const Acc<float> &a, int m) {
+    return Acc<float>{__shfl_xor(a.s, m), __shfl_xor(a.c, m)};
+}
+
+// Butterfly all-reduce; every combine is commutative, so all lanes end with
+// the same bits.
+template <typename T>
+__device__ __forceinline__ Acc<T> wave_allreduce(Acc<T> a) {
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) a = Acc<T>::combine(a, shfl_xor_acc(a, m));
+    return a;
+}
+
+// --------------------------------------------------------------------------------------------
+// occurrence loss of one event (Section III steps 1-3) for each layout
+template <typename T, int LAYOUT>
+struct Lookup;
+
+template <typename T>
+struct Lookup<T, kDirect> {
+    __device__ __forceinline__ static T occ(int32_t E, const TablesView &tb, const Terms<T> &t) {
+        const T *tab = static_cast<const T *>(tb.direct);
+        EventSum<T> s;
+        for (int j = 0; j < t.n_elts; ++j) {
+            T l = tab[(size_t)j * (size_t)tb.catalog + (size_t)E];
+            s.add(clamp_excess(l, t.ret[j], t.lim[j]));
+        }
+        return clamp_excess(s.value(), t.occ_ret, t.occ_lim);
+    }
+};
+
+template <typename T>
+struct Lookup<T, kSparse> {
+    __device__ __forceinline__ static T occ(int32_t E, const TablesView &tb, const Terms<T> &t) {
+        const T *loss = static_cast<const T *>(tb.sp_loss);
+        EventSum<T> s;
+        for (int j = 0; j < t.n_elts; ++j) {
+            int64_t lo = tb.sp_off[j], n = tb.sp_off[j + 1] - lo;
+            T l = T(0);
+            if (n > 0) {
+                // branch-free lower search: last index with id <= E
+                int64_t base = lo;
+                while (n > 1) {
+                    int64_t half = n >> 1;
+                    base = (tb.sp_ids[base + half] <= E) ? base + half : base;
+                    n -= half;
+                }
+                if (tb.sp_ids[base] == E) l = loss[base];
+            }
+            s.add(clamp_excess(l, t.ret[j], t.lim[j]));
+        }
+        return clamp_excess(s.value(), t.occ_ret, t.occ_lim);
+    }
+};
+
+template <typename T>
+struct Lookup<T, kCompact> {
+    __device__ __forceinline__ static T occ(int32_t E, const TablesView &tb, const Terms<T> &t) {
+        uint2 w = tb.bm[E >> 5];
+        uint32_t bit = 1u << (E & 31);
+        if (!(w.x & bit)) return T(0);  // in no ELT: every x_j and o are 0
+        int64_t idx = (int64_t)w.y + __popc(w.x & (bit - 1u));
+        const T *row = static_cast<const T *>(tb.rows) + idx * t.n_elts;
+        EventSum<T> s;
+        for (int j = 0; j < t.n_elts; ++j) s.add(clamp_excess(row[j], t.ret[j], t.lim[j]));
+        return clamp_excess(s.value(), t.occ_ret, t.occ_lim);
+    }
+};
+
+// --------------------------------------------------------------------------------------------
+// trial geometry
+struct TrialRange {
+    int64_t b, e;
+};
+
+__device__ __forceinline__ TrialRange trial_range(const YetView &y, int64_t i) {
+    if (y.offsets) return TrialRange{y.offsets[i], y.offsets[i + 1]};
+    return TrialRange{i * y.events_per_trial, (i + 1) * y.events_per_trial};
+}
+
+// Four event IDs at positions p..p+3; positions outside [b, e) read as -1.
+__device__ __forceinline__ void load4(const YetView &y, int64_t p, const TrialRange &r, int32_t id[4]) {
+    if (y.aligned16 && p >= r.b && p + 3 < r.e) {
+        int4 v = *reinterpret_cast<const int4 *>(y.ids + p);
+        id[0] = v.x; id[1] = v.y; id[2] = v.z; id[3] = v.w;
+    } else if (y.aligned16 && p + 3 < y.n_events) {
+        int4 v = *reinterpret_cast<const int4 *>(y.ids + p);
+        id[0] = v.x; id[1] = v.y; id[2] = v.z; id[3] = v.w;
+#pragma unroll
+        for (int v4 = 0; v4 < 4; ++v4)
+            if (p + v4 < r.b || p + v4 >= r.e) id[v4] = -1;
+    } else {
+#pragma unroll
+        for (int v4 = 0; v4 < 4; ++v4) {
+            int64_t q = p + v4;
+            id[v4] = (q >= r.b && q < r.e) ? y.ids[q] : -1;
+        }
+    }
+}
+
+__device__ __forceinline__ int64_t chunk_start(const YetView &y, int64_t b) { return y.aligned16 ? (b & ~3LL) : b; }
+
+// --------------------------------------------------------------------------------------------
+// kernels
+template <typename T, int LAYOUT>
+__global__ __launch_bounds__(256) void k_trial_pass(YetView y, TablesView tb, Terms<T> t, double *__restrict__ ylt) {
+    const int lane = lane_id();
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t trial = wave; trial < y.n_trials; trial += n_waves) {
+        const TrialRange r = trial_range(y, trial);
+        Acc<T> acc = Acc<T>::zero();
+        for (int64_t p = chunk_start(y, r.b) + 4 * lane; p < r.e; p += 4 * kWave) {
+            int32_t id[4];
+            load4(y, p, r, id);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (id[v] >= 0) acc.add(Lookup<T, LAYOUT>::occ(id[v], tb, t));
+        }
+        const double S = wave_allreduce(acc).value();
+        if (lane == 0) ylt[trial] = clamp_excess(S, t.agg_ret, t.agg_lim);
+    }
+}
+
+template <typename T, int LAYOUT>
+__global__ __launch_bounds__(256) void k_trial_pass_events(YetView y, TablesView tb, Terms<T> t,
+                                                           double *__restrict__ ylt, double *__restrict__ cum,
+                                                           double *__restrict__ net) {
+    const int lane = lane_id();
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t trial = wave; trial < y.n_trials; trial += n_waves) {
+        const TrialRange r = trial_range(y, trial);
+        Acc<T> carry = Acc<T>::zero();  // S after the previous chunk
+        double carry_net = 0.0;          // A after the previous chunk
+        for (int64_t c = chunk_start(y, r.b); c < r.e; c += 4 * kWave) {
+            const int64_t p = c + 4 * lane;
+            int32_t id[4];
+            load4(y, p, r, id);
+            Acc<T> pre[4];
+            Acc<T> run = Acc<T>::zero();
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (id[v] >= 0) run.add(Lookup<T, LAYOUT>::occ(id[v], tb, t));
+                pre[v] = run;
+            }
+            const Acc<T> incl = wave_inclusive_scan(run);
+            Acc<T> excl = shfl_acc(incl, lane > 0 ? lane - 1 : 0);
+            if (lane == 0) excl = Acc<T>::zero();
+            const Acc<T> base = Acc<T>::combine(carry, excl);
+            double Sv[4], Av[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                Sv[v] = Acc<T>::combine(base, pre[v]).value();
+                Av[v] = clamp_excess(Sv[v], t.agg_ret, t.agg_lim);
+            }
+            // A before this lane's first event: the previous lane's last A
+            double a_prev = __shfl(Av[3], lane > 0 ? lane - 1 : 0);
+            if (lane == 0) a_prev = carry_net;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (id[v] >= 0) {
+                    if (cum) cum[p + v] = Sv[v];
+                    if (net) net[p + v] = Av[v] - a_prev;
+                }
+                a_prev = Av[v];
+            }
+            carry = Acc<T>::combine(base, pre[3]);
+            carry = shfl_acc(carry, kWave - 1);
+            carry_net = __shfl(Av[3], kWave - 1);
+        }
+        if (lane == 0) ylt[trial] = clamp_excess(carry.value(), t.agg_ret, t.agg_lim);
+    }
+}
+
+__global__ void k_validate_yet(const int32_t *__restrict__ ids, int64_t n, int32_t catalog,
+                               const int64_t *__restrict__ off, int64_t n_trials, int32_t *flags) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int bad_id = 0, bad_off = 0;
+    for (int64_t i = tid; i < n; i += stride) bad_id |= ((uint32_t)ids[i] >= (uint32_t)catalog);
+    if (off) {
+        for (int64_t i = tid; i < n_trials; i += stride) bad_off |= (off[i + 1] < off[i]);
+        if (tid == 0) bad_off |= (off[0] != 0);
+    }
+    if (bad_id) atomicOr(&flags[0], 1);
+    if (bad_off) atomicOr(&flags[1], 1);
+}
+
+// --------------------------------------------------------------------------------------------
+int cu_count() {
+    static int cached[64] = {0};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64) dev = 0;
+    if (!cached[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cached[dev] = n;
+    }
+    return cached[dev];
+}
+
+int grid_for_trials(int64_t n_trials, int waves_per_block, int blocks_per_cu) {
+    int64_t need = (n_trials + waves_per_block - 1) / waves_per_block;
+    int64_t cap = (int64_t)cu_count() * blocks_per_cu;
+    int64_t g = need < cap ? need : cap;
+    return (int)(g < 1 ? 1 : g);
+}
+
+template <typename T>
+hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t, double *d_ylt, double *d_cum,
+                         double *d_net, bool events, hipStream_t s) {
+    if (y.n_trials == 0) return hipSuccess;
+    const int grid = grid_for_trials(y.n_trials, 4, 8);
+    const dim3 blk(256);
+    if (!events) {
+        switch (L.layout) {
+            case kDirect: hipLaunchKernelGGL((k_trial_pass<T, kDirect>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt); break;
+            case kSparse: hipLaunchKernelGGL((k_trial_pass<T, kSparse>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt); break;
+            default: hipLaunchKernelGGL((k_trial_pass<T, kCompact>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt); break;
+        }
+    } else {
+        switch (L.layout) {
+            case kDirect:
+                hipLaunchKernelGGL((k_trial_pass_events<T, kDirect>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt, d_cum, d_net);
+                break;
+            case kSparse:
+                hipLaunchKernelGGL((k_trial_pass_events<T, kSparse>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt, d_cum, d_net);
+                break;
+            default:
+                hipLaunchKernelGGL((k_trial_pass_events<T, kCompact>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt, d_cum, d_net);
+                break;
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_validate_yet(const YetView &y, int32_t catalog, int32_t *d_flags, hipStream_t s) {
+    const int grid = cu_count() * 4;
+    hipLaunchKernelGGL(k_validate_yet, dim3(grid), dim3(256), 0, s, y.ids, y.n_events, catalog, y.offsets, y.n_trials,
+                       d_flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_trial_pass(const YetView &y, const LayerHost &L, double *d_ylt, hipStream_t s) {
+    if (L.precision == ARA_FP32C) return launch_pass_t<float>(y, L, L.t32, d_ylt, nullptr, nullptr, false, s);
+    return launch_pass_t<double>(y, L, L.t64, d_ylt, nullptr, nullptr, false, s);
+}
+
+hipError_t launch_trial_pass_events(const YetView &y, const LayerHost &L, double *d_ylt, double *d_cum,
+                                    double *d_net, hipStream_t s) {
+    if (L.precision == ARA_FP32C) return launch_pass_t<float>(y, L, L.t32, d_ylt, d_cum, d_net, true, s);
+    return launch_pass_t<double>(y, L, L.t64, d_ylt, d_cum, d_net, true, s);
+}
+
+}  // namespace ara

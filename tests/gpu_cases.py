@@ -1,0 +1,53 @@
+"""Helpers shared by the GPU tests: run a case through the C-ABI and through
+the oracle on the same seeded inputs, and compare."""
+import numpy as np
+import torch
+
+from oracle import oracle
+from paper_1412_4556_amd import ara as A
+
+TOL = {"fp64": 1e-12, "fp32c": 1e-6}
+
+
+def gpu_layer_run(ids, off, T, C, K, spec, prec, layout, events=False, ids_misalign=False):
+    """YLT (and per-event outputs) of the HIP path, copied to the host."""
+    if ids_misalign:
+        # place the IDs one element into a bigger buffer: not 16-byte aligned
+        buf = torch.empty(len(ids) + 1, dtype=torch.int32, device="cuda")
+        buf[1:] = torch.from_numpy(np.ascontiguousarray(ids, np.int32)).cuda()
+        t_ids = buf[1:]
+        assert t_ids.data_ptr() % 16 != 0
+    else:
+        t_ids = torch.from_numpy(np.ascontiguousarray(ids, np.int32)).cuda()
+    t_off = None if off is None else torch.from_numpy(np.ascontiguousarray(off, np.int64)).cuda()
+    yet = A.Yet(t_ids, t_off, T, C, K)
+    lay = A.Layer(yet, spec, prec, layout)
+    if events:
+        y, cum, net = A.run_layer_events(yet, lay)
+        torch.cuda.synchronize()
+        out = (y.cpu().numpy(), cum.cpu().numpy(), net.cpu().numpy())
+    else:
+        y = A.run_layer(yet, lay)
+        torch.cuda.synchronize()
+        out = y.cpu().numpy()
+    lay.close()
+    yet.close()
+    return out
+
+
+def assert_close_to_oracle(y, ref, prec, what="ylt"):
+    """|y - y_ref| <= tol * G_i per trial, G_i the trial's gross looked-up loss."""
+    tol = TOL[prec]
+    G = ref["gross"]
+    err = np.abs(y - ref[what])
+    bad = err > tol * G
+    assert not bad.any(), (f"{what}: {bad.sum()} trials over {tol}*G; worst trial {int(np.argmax(err / np.maximum(G, 1e-300)))}"
+                           f" err {err.max():.3e}")
+    pos = ref[what] > 0
+    rel = float((err[pos] / ref[what][pos]).max()) if pos.any() else 0.0
+    scaled = float((err / np.maximum(G, 1e-300)).max()) if len(G) else 0.0
+    return {"max_err_over_gross": scaled, "max_rel_err": rel}
+
+
+def oracle_run(ids, off, T, C, K, spec, **kw):
+    return oracle.run_layer(ids, off, T, K, C, spec, n_threads=8, **kw)

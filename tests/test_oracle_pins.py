@@ -44,8 +44,10 @@ def test_worked_example_exact():
     g = json.load(open(GOLD))
     lay = _golden_layer(g)
     ids, off = _flatten(g["trials"])
-    r = _run(ids, off, g["catalog_size"], lay, want_event_net=True)
+    r = _run(ids, off, g["catalog_size"], lay, want_event_net=True, want_event_cum=True)
     assert r["ylt"].tolist() == g["ylt"]
+    cum = [r["event_cum"][off[i]:off[i + 1]].tolist() for i in range(len(off) - 1)]
+    assert cum == g["event_cum"]
     assert r["occ_sum"].tolist() == g["occ_sum"]
     net = [r["event_net"][off[i]:off[i + 1]].tolist() for i in range(len(off) - 1)]
     assert net == g["event_net"]

@@ -1,0 +1,257 @@
+"""Parity of the HIP trial pass (through the C-ABI) with the CPU oracle.
+
+Tolerances: every trial's |y - y_oracle| <= tol * G, G the trial's gross
+looked-up loss, tol = 1e-12 in FP64 and 1e-6 in FP32C; integer-valued cases
+must match bitwise.  Layouts must agree with each other bitwise.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_cases import TOL, assert_close_to_oracle, gpu_layer_run, oracle_run
+from oracle import oracle
+from paper_1412_4556_amd import _lib as L
+from paper_1412_4556_amd import ara as A
+from paper_1412_4556_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "worked_example.json")
+PRECS = ["fp64", "fp32c"]
+LAYOUTS = ["direct", "sparse", "compact"]
+
+
+def _golden():
+    g = json.load(open(GOLD))
+    spec = W.LayerSpec([np.array(e["ids"], np.int32) for e in g["elts"]],
+                       [np.array(e["losses"], np.float64) for e in g["elts"]],
+                       np.array([e["ret"] for e in g["elts"]], np.float64),
+                       np.array([e["lim"] for e in g["elts"]], np.float64),
+                       g["occ_ret"], g["occ_lim"], g["agg_ret"], g["agg_lim"])
+    off = np.zeros(len(g["trials"]) + 1, np.int64)
+    np.cumsum([len(t) for t in g["trials"]], out=off[1:])
+    ids = np.array([e for t in g["trials"] for e in t], np.int32)
+    return g, spec, ids, off
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_worked_example(prec, layout):
+    g, spec, ids, off = _golden()
+    T = len(off) - 1
+    y = gpu_layer_run(ids, off, T, g["catalog_size"], 0, spec, prec, layout)
+    assert y.tolist() == g["ylt"]
+    y2, cum, net = gpu_layer_run(ids, off, T, g["catalog_size"], 0, spec, prec, layout, events=True)
+    assert y2.tolist() == g["ylt"]
+    assert [cum[off[i]:off[i + 1]].tolist() for i in range(T)] == g["event_cum"]
+    assert [net[off[i]:off[i + 1]].tolist() for i in range(T)] == g["event_net"]
+
+
+def test_worked_example_pml_tvar():
+    g, *_ = _golden()
+    y = torch.tensor(g["ylt"], dtype=torch.float64, device="cuda")
+    pml, tvar = A.pml_tvar(y, g["pml_tvar"]["return_periods"])
+    assert pml.tolist() == g["pml_tvar"]["pml"]
+    assert tvar.tolist() == g["pml_tvar"]["tvar"]
+
+
+# ----------------------------------------------------------------------------- configured workloads
+@pytest.fixture(scope="module")
+def tiny():
+    wl = W.plain_tiny()
+    ids, off = W.yet_full(wl.yet)
+    spec = wl.layers[0]
+    ref = oracle_run(ids, None, wl.yet.n_trials, wl.yet.catalog_size, wl.yet.fixed_len, spec)
+    return wl, ids, spec, ref
+
+
+def test_plain_tiny_all_layouts(tiny):
+    wl, ids, spec, ref = tiny
+    T, C, K = wl.yet.n_trials, wl.yet.catalog_size, wl.yet.fixed_len
+    assert (ref["ylt"] > 0).mean() > 0.1  # the terms leave a non-degenerate YLT
+    results = {}
+    for prec in PRECS:
+        ys = {}
+        for layout in LAYOUTS:
+            ys[layout] = gpu_layer_run(ids, None, T, C, K, spec, prec, layout)
+            results[(prec, layout)] = assert_close_to_oracle(ys[layout], ref, prec)
+        for layout in LAYOUTS[1:]:
+            assert np.array_equal(ys[layout], ys["direct"]), (prec, layout)
+    print(results)
+    # risk metrics: on the GPU's own YLT the selection is exact and the mean
+    # is within binary64 rounding; against the oracle's YLT they move by at
+    # most the largest per-trial error
+    y = gpu_layer_run(ids, None, T, C, K, spec, "fp64", "compact")
+    gp, gt = A.pml_tvar(torch.from_numpy(y).cuda(), wl.return_periods)
+    op, ot = oracle.pml_tvar(y, wl.return_periods)
+    assert np.array_equal(gp, op)
+    assert np.allclose(gt, ot, rtol=1e-12, atol=0)
+    rp, rt = oracle.pml_tvar(ref["ylt"], wl.return_periods)
+    bound = TOL["fp64"] * ref["gross"].max()
+    assert np.all(np.abs(gp - rp) <= bound) and np.all(np.abs(gt - rt) <= bound)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_precision_workload(prec):
+    wl = W.precision_poisson()
+    ids, off = W.yet_full(wl.yet)
+    T, C = wl.yet.n_trials, wl.yet.catalog_size
+    for spec in wl.layers:
+        ref = oracle_run(ids, off, T, C, 0, spec)
+        y = gpu_layer_run(ids, off, T, C, 0, spec, prec, "compact")
+        stats = assert_close_to_oracle(y, ref, prec)
+        gp, gt = A.pml_tvar(torch.from_numpy(y).cuda(), wl.return_periods)
+        rp, rt = oracle.pml_tvar(ref["ylt"], wl.return_periods)
+        bound = TOL[prec] * ref["gross"].max()
+        assert np.all(np.abs(gp - rp) <= bound) and np.all(np.abs(gt - rt) <= bound)
+        print(spec.name, prec, stats, "pml rel err", np.abs(gp - rp) / rp, "tvar rel err", np.abs(gt - rt) / rt)
+        if spec.name == "pareto_uncapped_elt":
+            assert (ref["ylt"] > 0).mean() > 0.01
+
+
+# ----------------------------------------------------------------------------- edge cases
+EDGE = [
+    # id, kwargs of random_case, misalign
+    ("empties", dict(seed=31, n_trials=500, mean_len=30.0, catalog=800, n_elts=4, elt_size=200, empty_frac=0.3), False),
+    ("short_trials", dict(seed=32, n_trials=700, mean_len=2.0, catalog=300, n_elts=3, elt_size=100), False),
+    ("long_trials", dict(seed=33, n_trials=40, mean_len=3000.0, catalog=5000, n_elts=5, elt_size=1500), False),
+    ("misaligned_ids", dict(seed=34, n_trials=300, mean_len=57.0, catalog=900, n_elts=3, elt_size=300), True),
+    ("one_trial", dict(seed=35, n_trials=1, mean_len=999.0, catalog=600, n_elts=2, elt_size=300), False),
+    ("catalog_one", dict(seed=36, n_trials=50, mean_len=10.0, catalog=1, n_elts=2, elt_size=1), False),
+    ("max_elts", dict(seed=37, n_trials=200, mean_len=100.0, catalog=3000, n_elts=32, elt_size=300), False),
+    ("one_elt", dict(seed=38, n_trials=300, mean_len=100.0, catalog=3000, n_elts=1, elt_size=2000), False),
+    ("open_terms", dict(seed=39, n_trials=300, mean_len=100.0, catalog=3000, n_elts=4, elt_size=800, terms="open"), False),
+    ("counting", dict(seed=40, n_trials=300, mean_len=100.0, catalog=3000, n_elts=4, elt_size=800, terms="counting",
+                      integer_losses=True), False),
+]
+
+
+@pytest.mark.parametrize("name,kw,misalign", EDGE, ids=[e[0] for e in EDGE])
+@pytest.mark.parametrize("prec", PRECS)
+def test_edge_cases(name, kw, misalign, prec):
+    ids, off, spec = W.random_case(**kw)
+    T, C = kw["n_trials"], kw["catalog"]
+    ref = oracle_run(ids, off, T, C, 0, spec, want_event_cum=True, want_event_net=True)
+    ys = [gpu_layer_run(ids, off, T, C, 0, spec, prec, lay, ids_misalign=misalign) for lay in LAYOUTS]
+    assert_close_to_oracle(ys[0], ref, prec)
+    assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2])
+    y, cum, net = gpu_layer_run(ids, off, T, C, 0, spec, prec, "compact", events=True, ids_misalign=misalign)
+    assert_close_to_oracle(y, ref, prec)
+    gross_ev = np.repeat(ref["gross"], np.diff(off))
+    assert np.all(np.abs(cum - ref["event_cum"]) <= TOL[prec] * gross_ev)
+    assert np.all(np.abs(net - ref["event_net"]) <= 2 * TOL[prec] * gross_ev)
+
+
+@pytest.mark.parametrize("K", [0, 1, 3, 7, 256, 1000, 1001])
+def test_fixed_length_trials(K):
+    T, C = 257, 2000
+    rng = np.random.default_rng(K)
+    ids = rng.integers(0, C, size=T * K, dtype=np.int32)
+    _, _, spec = W.random_case(41, 1, 1.0, C, 4, 600)
+    ref = oracle_run(ids, None, T, C, K, spec)
+    for prec in PRECS:
+        y = gpu_layer_run(ids, None, T, C, K, spec, prec, "compact")
+        assert_close_to_oracle(y, ref, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_integer_cases_are_bitwise(prec):
+    for seed in (51, 52, 53):
+        ids, off, spec = W.random_case(seed, 400, 300.0, 4000, 4, 1500, integer_losses=True, max_int_loss=60)
+        ref = oracle_run(ids, off, 400, 4000, 0, spec, want_event_cum=True, want_event_net=True)
+        for layout in LAYOUTS:
+            y = gpu_layer_run(ids, off, 400, 4000, 0, spec, prec, layout)
+            assert np.array_equal(y, ref["ylt"]), (seed, layout)
+        y, cum, net = gpu_layer_run(ids, off, 400, 4000, 0, spec, prec, "compact", events=True)
+        assert np.array_equal(y, ref["ylt"]) and np.array_equal(cum, ref["event_cum"])
+        assert np.array_equal(net, ref["event_net"])
+
+
+def test_zero_trials():
+    ids = np.zeros(0, np.int32)
+    off = np.zeros(1, np.int64)
+    _, _, spec = W.random_case(42, 1, 1.0, 100, 2, 50)
+    y = gpu_layer_run(ids, off, 0, 100, 0, spec, "fp64", "compact")
+    assert y.shape == (0,)
+
+
+def test_runs_are_deterministic():
+    ids, off, spec = W.random_case(43, 2000, 200.0, 20000, 8, 3000)
+    a = gpu_layer_run(ids, off, 2000, 20000, 0, spec, "fp32c", "compact")
+    b = gpu_layer_run(ids, off, 2000, 20000, 0, spec, "fp32c", "compact")
+    assert np.array_equal(a, b)
+
+
+# ----------------------------------------------------------------------------- risk metrics
+@pytest.mark.parametrize("T,N", [(1, 1), (1000, 100), (1000, 250), (997, 10), (100_000, 250), (1_000_000, 100)])
+def test_pml_tvar_permutation(T, N):
+    y = np.random.default_rng(T).permutation(np.arange(1, T + 1)).astype(np.float64)
+    pml, tvar = A.pml_tvar(torch.from_numpy(y).cuda(), [N])
+    k = T // N
+    assert pml[0] == T - k + 1
+    assert tvar[0] == T - (k - 1) / 2
+
+
+def test_pml_tvar_ties_zeros_negatives():
+    rng = np.random.default_rng(7)
+    y = np.concatenate([np.zeros(5000), np.full(300, 7.5), rng.lognormal(5, 1, 700), -rng.uniform(0, 5, 100)])
+    rng.shuffle(y)
+    Ns = [1, 2, 10, 17, 100, 6100]
+    gp, gt = A.pml_tvar(torch.from_numpy(y).cuda(), Ns)
+    op, ot = oracle.pml_tvar(y, Ns)
+    assert np.array_equal(gp, op)
+    assert np.allclose(gt, ot, rtol=1e-12, atol=1e-300)
+
+
+def test_pml_tvar_errors():
+    y = torch.ones(10, dtype=torch.float64, device="cuda")
+    with pytest.raises(L.AraError) as ei:
+        A.pml_tvar(y, [100])
+    assert ei.value.name == "ARA_ERR_RP"
+    y[3] = float("nan")
+    with pytest.raises(L.AraError) as ei:
+        A.pml_tvar(y, [2])
+    assert ei.value.name == "ARA_ERR_VALUE"
+
+
+# ----------------------------------------------------------------------------- error paths
+def test_create_errors():
+    ids = torch.tensor([0, 1, 2, 5], dtype=torch.int32, device="cuda")
+    with pytest.raises(L.AraError) as ei:
+        A.Yet(ids, None, 2, 5, 2)
+    assert ei.value.name == "ARA_ERR_EVENT_RANGE"
+    bad_off = torch.tensor([0, 3, 2, 4], dtype=torch.int64, device="cuda")
+    with pytest.raises(L.AraError) as ei:
+        A.Yet(ids, bad_off, 3, 10)
+    assert ei.value.name == "ARA_ERR_INVALID_ARG"
+    yet = A.Yet(ids, None, 2, 10, 2)
+    one = lambda ids_, loss: W.LayerSpec([np.array(ids_, np.int32)], [np.array(loss, np.float64)],
+                                               np.zeros(1), np.full(1, np.inf), 0.0, np.inf, 0.0, np.inf)
+    with pytest.raises(L.AraError) as ei:
+        A.Layer(yet, one([1, 1], [1.0, 2.0]))
+    assert ei.value.name == "ARA_ERR_DUP_EVENT"
+    with pytest.raises(L.AraError) as ei:
+        A.Layer(yet, one([1, 11], [1.0, 2.0]))
+    assert ei.value.name == "ARA_ERR_EVENT_RANGE"
+    with pytest.raises(L.AraError) as ei:
+        A.Layer(yet, one([1, 2], [1.0, -2.0]))
+    assert ei.value.name == "ARA_ERR_VALUE"
+    with pytest.raises(L.AraError) as ei:
+        A.Layer(yet, one([1, 2], [1.0, float("nan")]))
+    assert ei.value.name == "ARA_ERR_VALUE"
+    spec = one([1], [1.0]).with_terms(occ_ret=-1.0)
+    with pytest.raises(L.AraError) as ei:
+        A.Layer(yet, spec)
+    assert ei.value.name == "ARA_ERR_VALUE"
+    big = W.LayerSpec([np.array([i % 10], np.int32) for i in range(33)], [np.ones(1)] * 33, np.zeros(33),
+                      np.full(33, np.inf), 0, np.inf, 0, np.inf)
+    with pytest.raises(L.AraError) as ei:
+        A.Layer(yet, big)
+    assert ei.value.name == "ARA_ERR_UNSUPPORTED"
+    # a valid layer still works after the failures
+    lay = A.Layer(yet, one([0, 5], [3.0, 4.0]))
+    y = A.run_layer(yet, lay).cpu().numpy()
+    assert y.tolist() == [3.0, 4.0]
