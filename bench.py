@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
-    ap.add_argument("--layout", default="auto", choices=["auto", "direct", "sparse", "compact"])
+    ap.add_argument("--layout", default="auto", choices=["auto", "direct", "sparse", "compact", "fused"])
     ap.add_argument("--trials", type=int, default=1_000_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -143,8 +143,8 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        for prec, layout, steps in (("fp32c", args.layout, args.steps), ("fp64", "direct", 3), ("fp32c", "direct", 3),
-                                    ("fp64", "sparse", 2), ("fp64", "compact", 3)):
+        for prec, layout, steps in (("fp32c", args.layout, args.steps), ("fp64", "compact", 5), ("fp32c", "compact", 5),
+                                    ("fp64", "direct", 3), ("fp32c", "direct", 3), ("fp64", "sparse", 2)):
             if prec == args.precision and layout == args.layout:
                 continue
             l2 = A.Layer(yet, spec, prec, layout)
@@ -197,7 +197,8 @@ def main():
         "hbm_gbps_algorithmic": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBPS, "traffic": None,
-                     "kernel": "k_trial_pass", "algorithmic_bytes": algo_bytes},
+                     "kernel": "k_trial_pass_fused" if lay.layout == "fused" else "k_trial_pass",
+                     "algorithmic_bytes": algo_bytes},
         "cpu_baseline": cpu,
         "pml": pml.tolist(),
         "tvar": tvar.tolist(),

@@ -73,13 +73,22 @@ typedef enum { ARA_FP64 = 0, ARA_FP32C = 1 } ara_precision;
  *   ARA_LAYOUT_COMPACT : a presence bitmap over the catalogue with per-word
  *                        ranks, and one row of J losses per event present in
  *                        any ELT of the layer (event-major).
- *   ARA_LAYOUT_AUTO    : the library's choice (currently COMPACT).
+ *   ARA_LAYOUT_FUSED   : the occurrence loss of every catalogue event,
+ *                        o(E) = FT2(sum_j FT1_j(l_j(E))), computed once when
+ *                        the layer is built (steps 1-3 depend on the event
+ *                        only, not on the trial: occurrence terms apply to
+ *                        each occurrence independently of the others), kept
+ *                        as a catalogue-sized table, plus a bitmap of the
+ *                        blocks of events whose o is non-zero that the trial
+ *                        pass holds in LDS.  Same arithmetic, same order.
+ *   ARA_LAYOUT_AUTO    : the library's choice (currently FUSED).
  * Every layout gives bitwise the same YLT for the same precision. */
 typedef enum {
     ARA_LAYOUT_AUTO = 0,
     ARA_LAYOUT_DIRECT = 1,
     ARA_LAYOUT_SPARSE = 2,
-    ARA_LAYOUT_COMPACT = 3
+    ARA_LAYOUT_COMPACT = 3,
+    ARA_LAYOUT_FUSED = 4
 } ara_layout;
 
 /* Register a device-resident YET (Section III: trials of event IDs ordered by

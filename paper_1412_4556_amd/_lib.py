@@ -23,7 +23,7 @@ ERRORS = {
     -8: "ARA_ERR_UNSUPPORTED",
 }
 ARA_FP64, ARA_FP32C = 0, 1
-ARA_LAYOUT_AUTO, ARA_LAYOUT_DIRECT, ARA_LAYOUT_SPARSE, ARA_LAYOUT_COMPACT = 0, 1, 2, 3
+ARA_LAYOUT_AUTO, ARA_LAYOUT_DIRECT, ARA_LAYOUT_SPARSE, ARA_LAYOUT_COMPACT, ARA_LAYOUT_FUSED = 0, 1, 2, 3, 4
 ARA_MAX_ELTS = 32
 
 _P = ctypes.c_void_p

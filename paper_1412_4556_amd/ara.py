@@ -16,7 +16,7 @@ from . import _lib as L
 
 PRECISIONS = {"fp64": L.ARA_FP64, "fp32c": L.ARA_FP32C}
 LAYOUTS = {"auto": L.ARA_LAYOUT_AUTO, "direct": L.ARA_LAYOUT_DIRECT, "sparse": L.ARA_LAYOUT_SPARSE,
-           "compact": L.ARA_LAYOUT_COMPACT}
+           "compact": L.ARA_LAYOUT_COMPACT, "fused": L.ARA_LAYOUT_FUSED}
 LAYOUT_NAMES = {v: k for k, v in LAYOUTS.items()}
 
 

@@ -78,11 +78,21 @@ ara_status upload(ara::LayerHost &h, int slot, const T *src, size_t count, const
     h.alloc[slot] = d;
     h.bytes += count * sizeof(T);
     if (count) {
-        e = hipMemcpy(d, src, count * sizeof(T), hipMemcpyHostToDevice);
+        hipStream_t s = ara::internal_stream();
+        e = hipMemcpyAsync(d, src, count * sizeof(T), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "copy of layer tables");
     }
     *dst = d;
     return ARA_OK;
+}
+
+void release_slot(ara::LayerHost &h, int slot, size_t bytes) {
+    if (h.alloc[slot]) {
+        (void)hipFree(h.alloc[slot]);
+        h.alloc[slot] = nullptr;
+        h.bytes -= bytes;
+    }
 }
 
 template <typename T>
@@ -155,12 +165,46 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
                 size_t idx = (size_t)w.y + (size_t)__builtin_popcount(w.x & (bit - 1u));
                 rows[idx * J + j] = (T)loss[start[j] + n];
             }
-        const void *d0, *d1;
-        if ((st = upload(h, 0, bm.data(), bm.size(), &d0)) != ARA_OK) return st;
-        if ((st = upload(h, 1, rows.data(), rows.size(), &d1)) != ARA_OK) return st;
-        h.tab.bm = static_cast<const uint2 *>(d0);
-        h.tab.rows = d1;
-        h.tab.n_words = (int32_t)n_words;
+        if (h.layout == ara::kCompact) {
+            const void *d0, *d1;
+            if ((st = upload(h, 0, bm.data(), bm.size(), &d0)) != ARA_OK) return st;
+            if ((st = upload(h, 1, rows.data(), rows.size(), &d1)) != ARA_OK) return st;
+            h.tab.bm = static_cast<const uint2 *>(d0);
+            h.tab.rows = d1;
+            h.tab.n_words = (int32_t)n_words;
+        } else {
+            // fused: occurrence loss per catalogue event and the LDS filter
+            std::vector<int32_t> present;
+            present.reserve(rank);
+            for (int64_t w = 0; w < n_words; ++w)
+                for (uint32_t x = bm[w].x; x; x &= x - 1u) present.push_back((int32_t)(w * 32 + __builtin_ctz(x)));
+            int32_t fshift = 0;
+            while ((((int64_t)C + (1LL << fshift) - 1) >> fshift) > ara::kFilterBits) ++fshift;
+            const int64_t n_blocks = ((int64_t)C + (1LL << fshift) - 1) >> fshift;
+            const int64_t n_fwords = (n_blocks + 31) / 32;
+            const void *d_rows, *d_present;
+            if ((st = upload(h, 0, rows.data(), rows.size(), &d_rows)) != ARA_OK) return st;
+            if ((st = upload(h, 1, present.data(), present.size(), &d_present)) != ARA_OK) return st;
+            void *d_occ = nullptr, *d_filt = nullptr;
+            hipError_t e = dev_alloc(&d_occ, (size_t)C * sizeof(T));
+            if (e != hipSuccess) return hip_fail(e, "device allocation of the fused table");
+            h.alloc[2] = d_occ;
+            h.bytes += (size_t)C * sizeof(T);
+            e = dev_alloc(&d_filt, (size_t)n_fwords * sizeof(uint32_t));
+            if (e != hipSuccess) return hip_fail(e, "device allocation of the fused filter");
+            h.alloc[3] = d_filt;
+            h.bytes += (size_t)n_fwords * sizeof(uint32_t);
+            h.tab.occ = d_occ;
+            h.tab.filt = static_cast<const uint32_t *>(d_filt);
+            h.tab.fshift = fshift;
+            h.tab.n_fwords = (int32_t)n_fwords;
+            hipStream_t s = ara::internal_stream();
+            e = ara::launch_fuse(h, d_rows, static_cast<const int32_t *>(d_present), (int64_t)rank, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e, "building the fused table");
+            release_slot(h, 0, rows.size() * sizeof(T));
+            release_slot(h, 1, present.size() * sizeof(int32_t));
+        }
     }
     return ARA_OK;
 }
@@ -240,7 +284,7 @@ ara_status ara_create_layer(ara_yet yet, int32_t n_elts, const int32_t *h_elt_id
     if (n_elts < 1) return fail(ARA_ERR_INVALID_ARG, "n_elts < 1");
     if (n_elts > ARA_MAX_ELTS) return fail(ARA_ERR_UNSUPPORTED, "n_elts exceeds ARA_MAX_ELTS");
     if (precision != ARA_FP64 && precision != ARA_FP32C) return fail(ARA_ERR_INVALID_ARG, "unknown precision");
-    if (layout < ARA_LAYOUT_AUTO || layout > ARA_LAYOUT_COMPACT) return fail(ARA_ERR_INVALID_ARG, "unknown layout");
+    if (layout < ARA_LAYOUT_AUTO || layout > ARA_LAYOUT_FUSED) return fail(ARA_ERR_INVALID_ARG, "unknown layout");
     if (!h_elt_sizes || !h_ret || !h_lim) return fail(ARA_ERR_INVALID_ARG, "NULL term or size array");
     const int32_t C = yet->catalog;
     std::vector<int64_t> start(n_elts + 1, 0);
@@ -279,7 +323,7 @@ ara_status ara_create_layer(ara_yet yet, int32_t n_elts, const int32_t *h_elt_id
     h.n_elts = n_elts;
     h.catalog = C;
     h.precision = precision;
-    h.layout = layout == ARA_LAYOUT_AUTO ? ARA_LAYOUT_COMPACT : layout;
+    h.layout = layout == ARA_LAYOUT_AUTO ? ARA_LAYOUT_FUSED : layout;
     h.tab.catalog = C;
     for (int j = 0; j < n_elts; ++j) {
         h.t64.ret[j] = h_ret[j];

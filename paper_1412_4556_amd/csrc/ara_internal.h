@@ -45,11 +45,26 @@ struct TablesView {
     // events below 32w}; rows[rank][n_elts] losses of present events
     const uint2 *bm;
     const void *rows;
+    // FUSED: occ[catalog] occurrence loss of every event; bit b of filt[w] is
+    // set iff an event of block 32w+b (a block being 2^fshift consecutive
+    // events) has a non-zero occurrence loss
+    const void *occ;
+    const uint32_t *filt;
+    int32_t n_fwords;
+    int32_t fshift;
     int32_t catalog;
     int32_t n_words;
 };
 
-enum Layout : int32_t { kDirect = ARA_LAYOUT_DIRECT, kSparse = ARA_LAYOUT_SPARSE, kCompact = ARA_LAYOUT_COMPACT };
+// Largest filter the fused pass keeps in LDS (bits): 128 KiB.
+constexpr int64_t kFilterBits = 1 << 20;
+
+enum Layout : int32_t {
+    kDirect = ARA_LAYOUT_DIRECT,
+    kSparse = ARA_LAYOUT_SPARSE,
+    kCompact = ARA_LAYOUT_COMPACT,
+    kFused = ARA_LAYOUT_FUSED
+};
 
 struct LayerHost {
     int32_t n_elts = 0;
@@ -65,7 +80,13 @@ struct LayerHost {
     void *alloc[6] = {};
 };
 
+// A non-blocking stream of the library for its own set-up work (one per device).
+hipStream_t internal_stream();
+
 // Launchers (ara_kernels.hip).  Return a hipError_t.
+// Fused tables: occ[] from the compact rows (rows[n_present][n_elts],
+// present_ids[n_present]), then the LDS filter bits.
+hipError_t launch_fuse(LayerHost &L, const void *d_rows, const int32_t *d_present, int64_t n_present, hipStream_t s);
 hipError_t launch_validate_yet(const YetView &y, int32_t catalog, int32_t *d_flags, hipStream_t s);
 hipError_t launch_trial_pass(const YetView &y, const LayerHost &L, double *d_ylt, hipStream_t s);
 hipError_t launch_trial_pass_events(const YetView &y, const LayerHost &L, double *d_ylt, double *d_cum,

@@ -211,6 +211,13 @@ struct Lookup<T, kCompact> {
     }
 };
 
+template <typename T>
+struct Lookup<T, kFused> {
+    __device__ __forceinline__ static T occ(int32_t E, const TablesView &tb, const Terms<T> &) {
+        return static_cast<const T *>(tb.occ)[E];
+    }
+};
+
 // --------------------------------------------------------------------------------------------
 // trial geometry
 struct TrialRange {
@@ -317,6 +324,83 @@ __global__ __launch_bounds__(256) void k_trial_pass_events(YetView y, TablesView
     }
 }
 
+// Fused layout: the pass needs one LDS filter probe per event and one gather
+// of the precomputed occurrence loss only for events whose block is marked.
+// Events are added in the same order as in k_trial_pass, and skipped events
+// would add exactly zero, so the YLT is bitwise the one of the other layouts.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const uint32_t *__restrict__ filt,
+                                                           int32_t n_fwords, int32_t fshift, const T *__restrict__ occ,
+                                                           double agg_ret, double agg_lim, double *__restrict__ ylt) {
+    extern __shared__ uint32_t sfilt[];
+    for (int i = threadIdx.x; i < n_fwords; i += blockDim.x) sfilt[i] = filt[i];
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t trial = wave; trial < y.n_trials; trial += n_waves) {
+        const TrialRange r = trial_range(y, trial);
+        Acc<T> acc = Acc<T>::zero();
+        for (int64_t p = chunk_start(y, r.b) + 4 * lane; p < r.e; p += 4 * kWave) {
+            int32_t id[4];
+            load4(y, p, r, id);
+            bool hit[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t blk = id[v] >= 0 ? ((uint32_t)id[v] >> fshift) : 0u;
+                hit[v] = id[v] >= 0 && ((sfilt[blk >> 5] >> (blk & 31)) & 1u);
+            }
+            T o[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[v] = hit[v] ? occ[id[v]] : T(0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (hit[v]) acc.add(o[v]);
+        }
+        const double S = wave_allreduce(acc).value();
+        if (lane == 0) ylt[trial] = clamp_excess(S, agg_ret, agg_lim);
+    }
+}
+
+template <typename T>
+__global__ void k_fill_zero(T *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = T(0);
+}
+
+// occ[E] for every event present in some ELT: the same arithmetic, in the
+// same order, as the per-event lookup of the compact layout.
+template <typename T>
+__global__ void k_fuse(const T *__restrict__ rows, const int32_t *__restrict__ present, int64_t n_present, Terms<T> t,
+                       T *__restrict__ occ) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_present;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T *row = rows + i * t.n_elts;
+        EventSum<T> s;
+        for (int j = 0; j < t.n_elts; ++j) s.add(clamp_excess(row[j], t.ret[j], t.lim[j]));
+        occ[present[i]] = clamp_excess(s.value(), t.occ_ret, t.occ_lim);
+    }
+}
+
+template <typename T>
+__global__ void k_build_filter(const T *__restrict__ occ, int64_t catalog, int32_t fshift, uint32_t *__restrict__ filt,
+                               int32_t n_fwords) {
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_fwords; w += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t bits = 0;
+        for (int b = 0; b < 32; ++b) {
+            const int64_t lo = ((w << 5) + b) << fshift;
+            int64_t hi = lo + (1LL << fshift);
+            if (hi > catalog) hi = catalog;
+            for (int64_t e = lo; e < hi; ++e)
+                if (occ[e] != T(0)) {
+                    bits |= 1u << b;
+                    break;
+                }
+        }
+        filt[w] = bits;
+    }
+}
+
 __global__ void k_validate_yet(const int32_t *__restrict__ ids, int64_t n, int32_t catalog,
                                const int64_t *__restrict__ off, int64_t n_trials, int32_t *flags) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -358,6 +442,22 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
     if (y.n_trials == 0) return hipSuccess;
     const int grid = grid_for_trials(y.n_trials, 4, 8);
     const dim3 blk(256);
+    if (!events && L.layout == kFused) {
+        const size_t lds = (size_t)L.tab.n_fwords * sizeof(uint32_t);
+        static bool attr_set[2] = {false, false};
+        const int which = sizeof(T) == 8 ? 0 : 1;
+        if (!attr_set[which]) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_trial_pass_fused<T>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kFilterBits / 8));
+            if (e != hipSuccess) return e;
+            attr_set[which] = true;
+        }
+        const int per_cu = lds > 80 * 1024 ? 1 : 2;
+        const int fgrid = grid_for_trials(y.n_trials, 16, per_cu);
+        hipLaunchKernelGGL((k_trial_pass_fused<T>), dim3(fgrid), dim3(1024), lds, s, y, L.tab.filt, L.tab.n_fwords,
+                           L.tab.fshift, static_cast<const T *>(L.tab.occ), t.agg_ret, t.agg_lim, d_ylt);
+        return hipGetLastError();
+    }
     if (!events) {
         switch (L.layout) {
             case kDirect: hipLaunchKernelGGL((k_trial_pass<T, kDirect>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt); break;
@@ -372,6 +472,9 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
             case kSparse:
                 hipLaunchKernelGGL((k_trial_pass_events<T, kSparse>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt, d_cum, d_net);
                 break;
+            case kFused:
+                hipLaunchKernelGGL((k_trial_pass_events<T, kFused>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt, d_cum, d_net);
+                break;
             default:
                 hipLaunchKernelGGL((k_trial_pass_events<T, kCompact>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt, d_cum, d_net);
                 break;
@@ -381,6 +484,40 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
 }
 
 }  // namespace
+
+hipStream_t internal_stream() {
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    dev &= 63;
+    if (!streams[dev]) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        streams[dev] = st;
+    }
+    return streams[dev];
+}
+
+namespace {
+template <typename T>
+hipError_t fuse_t(LayerHost &L, const Terms<T> &t, const void *d_rows, const int32_t *d_present, int64_t n_present,
+                  hipStream_t s) {
+    T *occ = static_cast<T *>(const_cast<void *>(L.tab.occ));
+    const int g = cu_count() * 4;
+    hipLaunchKernelGGL((k_fill_zero<T>), dim3(g), dim3(256), 0, s, occ, (int64_t)L.catalog);
+    if (n_present > 0)
+        hipLaunchKernelGGL((k_fuse<T>), dim3(g), dim3(256), 0, s, static_cast<const T *>(d_rows), d_present, n_present,
+                           t, occ);
+    hipLaunchKernelGGL((k_build_filter<T>), dim3(g), dim3(256), 0, s, occ, (int64_t)L.catalog, L.tab.fshift,
+                       const_cast<uint32_t *>(L.tab.filt), L.tab.n_fwords);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_fuse(LayerHost &L, const void *d_rows, const int32_t *d_present, int64_t n_present, hipStream_t s) {
+    if (L.precision == ARA_FP32C) return fuse_t<float>(L, L.t32, d_rows, d_present, n_present, s);
+    return fuse_t<double>(L, L.t64, d_rows, d_present, n_present, s);
+}
 
 hipError_t launch_validate_yet(const YetView &y, int32_t catalog, int32_t *d_flags, hipStream_t s) {
     const int grid = cu_count() * 4;

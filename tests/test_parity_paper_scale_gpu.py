@@ -32,7 +32,7 @@ def paper():
     return wl, yet, spec, sample, ref
 
 
-@pytest.mark.parametrize("prec,layout", [("fp64", "compact"), ("fp32c", "compact"), ("fp64", "direct"),
+@pytest.mark.parametrize("prec,layout", [("fp64", "fused"), ("fp32c", "fused"), ("fp64", "compact"), ("fp64", "direct"),
                                          ("fp32c", "direct"), ("fp64", "sparse")])
 def test_paper_scale_sampled(paper, prec, layout):
     wl, yet, spec, sample, ref = paper
