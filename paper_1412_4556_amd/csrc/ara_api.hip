@@ -186,10 +186,11 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
             if ((st = upload(h, 0, rows.data(), rows.size(), &d_rows)) != ARA_OK) return st;
             if ((st = upload(h, 1, present.data(), present.size(), &d_present)) != ARA_OK) return st;
             void *d_occ = nullptr, *d_filt = nullptr;
-            hipError_t e = dev_alloc(&d_occ, (size_t)C * sizeof(T));
+            // catalogue + 1 entries: occ[C] stays 0 for the pass's unmarked lanes
+            hipError_t e = dev_alloc(&d_occ, ((size_t)C + 1) * sizeof(T));
             if (e != hipSuccess) return hip_fail(e, "device allocation of the fused table");
             h.alloc[2] = d_occ;
-            h.bytes += (size_t)C * sizeof(T);
+            h.bytes += ((size_t)C + 1) * sizeof(T);
             e = dev_alloc(&d_filt, (size_t)n_fwords * sizeof(uint32_t));
             if (e != hipSuccess) return hip_fail(e, "device allocation of the fused filter");
             h.alloc[3] = d_filt;

@@ -45,7 +45,8 @@ struct TablesView {
     // events below 32w}; rows[rank][n_elts] losses of present events
     const uint2 *bm;
     const void *rows;
-    // FUSED: occ[catalog] occurrence loss of every event; bit b of filt[w] is
+    // FUSED: occ[catalog + 1] occurrence loss of every event (occ[catalog] = 0);
+    // bit b of filt[w] is
     // set iff an event of block 32w+b (a block being 2^fshift consecutive
     // events) has a non-zero occurrence loss
     const void *occ;

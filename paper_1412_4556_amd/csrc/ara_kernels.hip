@@ -231,7 +231,9 @@ __device__ __forceinline__ TrialRange trial_range(const YetView &y, int64_t i) {
 
 // Four event IDs at positions p..p+3; positions outside [b, e) read as -1.
 __device__ __forceinline__ void load4(const YetView &y, int64_t p, const TrialRange &r, int32_t id[4]) {
-    if (y.aligned16 && p >= r.b && p + 3 < r.e) {
+    if (p >= r.e) {
+        id[0] = id[1] = id[2] = id[3] = -1;
+    } else if (y.aligned16 && p >= r.b && p + 3 < r.e) {
         int4 v = *reinterpret_cast<const int4 *>(y.ids + p);
         id[0] = v.x; id[1] = v.y; id[2] = v.z; id[3] = v.w;
     } else if (y.aligned16 && p + 3 < y.n_events) {
@@ -326,39 +328,156 @@ __global__ __launch_bounds__(256) void k_trial_pass_events(YetView y, TablesView
 
 // Fused layout: the pass needs one LDS filter probe per event and one gather
 // of the precomputed occurrence loss only for events whose block is marked.
-// Events are added in the same order as in k_trial_pass, and skipped events
-// would add exactly zero, so the YLT is bitwise the one of the other layouts.
+// A wave loads a whole group of kGroup chunks (kGroup * 256 events) of a
+// trial at once and, before it works on the current trial, already issues the
+// loads of its next trial, so every lane keeps 2 * kGroup 16-byte loads in
+// flight.  Each lane still adds its events in the order of k_trial_pass (chunk
+// by chunk, four consecutive events per chunk) and skipped events would add
+// exactly zero, so the YLT is bitwise the one of the other layouts.
+#ifndef ARA_FUSED_GROUP
+#define ARA_FUSED_GROUP 4
+#endif
+constexpr int kGroup = ARA_FUSED_GROUP;
+
+struct IdGroup {
+    int32_t id[kGroup][4];
+};
+
+// ID loads of the fused pass.  With a 16-byte aligned YET every lane issues
+// its kGroup 16-byte loads unconditionally (a conditional load makes the
+// compiler wait for it inside the branch, which serialises the loads): the
+// address is clamped to the last 16-byte granule that holds a YET element, so
+// a load never leaves the granules of the buffer, and positions outside the
+// trial are masked afterwards (their IDs replaced by 0).
+//   FIXED: every trial holds the same non-zero multiple of 4 events, so a
+//          lane's four IDs are wholly inside or wholly past the trial.
+//   !ALIGNED: element loads with bounds checks (slow path, any alignment).
+template <bool FIXED, bool ALIGNED>
+__device__ __forceinline__ uint32_t load_group(const YetView &y, const TrialRange &r, int64_t base, int lane,
+                                               int64_t last_granule, IdGroup &g) {
+    uint32_t valid = 0;  // bit 4c+v: element v of chunk c lies in the trial
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) {
+        const int64_t p = base + c * 4 * kWave + 4 * lane;
+        if (ALIGNED) {
+            const int64_t q = p < last_granule ? p : last_granule;
+            const int4 v = *reinterpret_cast<const int4 *>(y.ids + q);
+            g.id[c][0] = v.x; g.id[c][1] = v.y; g.id[c][2] = v.z; g.id[c][3] = v.w;
+            if (FIXED) {
+                valid |= (p < r.e ? 0xfu : 0u) << (4 * c);
+            } else {
+                const int64_t lo64 = r.b - p, hi64 = r.e - p;
+                const int lo = lo64 < 0 ? 0 : (int)(lo64 > 4 ? 4 : lo64);
+                const int hi = hi64 < 0 ? 0 : (int)(hi64 > 4 ? 4 : hi64);
+#pragma unroll
+                for (int v4 = 0; v4 < 4; ++v4) {
+                    const bool in = (v4 >= lo) & (v4 < hi);
+                    g.id[c][v4] = in ? g.id[c][v4] : 0;
+                    valid |= (in ? 1u : 0u) << (4 * c + v4);
+                }
+            }
+        } else {
+            load4(y, p, r, g.id[c]);
+#pragma unroll
+            for (int v4 = 0; v4 < 4; ++v4) {
+                valid |= (g.id[c][v4] >= 0 ? 1u : 0u) << (4 * c + v4);
+                g.id[c][v4] = g.id[c][v4] >= 0 ? g.id[c][v4] : 0;
+            }
+        }
+    }
+    return valid;
+}
+
+// Occurrence losses of a group: an LDS filter probe per event, then a gather
+// for every event -- of occ[E] where E's block is marked, else of the zero at
+// occ[catalog] -- so no load sits under a branch.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const uint32_t *__restrict__ filt,
-                                                           int32_t n_fwords, int32_t fshift, const T *__restrict__ occ,
-                                                           double agg_ret, double agg_lim, double *__restrict__ ylt) {
+__device__ __forceinline__ void gather_group(const IdGroup &g, uint32_t valid, const uint32_t *sfilt, int32_t fshift,
+                                             int32_t zero_slot, const T *__restrict__ occ, T (&o)[kGroup][4]) {
+    int32_t idx[kGroup][4];
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint32_t blk = (uint32_t)g.id[c][v] >> fshift;
+            const uint32_t hit = ((valid >> (4 * c + v)) & 1u) & __builtin_amdgcn_ubfe(sfilt[blk >> 5], blk, 1u);
+            idx[c][v] = hit ? g.id[c][v] : zero_slot;
+        }
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[c][v] = occ[idx[c][v]];
+}
+
+// Adds in k_trial_pass order; adding an exact zero changes no bit of the sum.
+template <typename T>
+__device__ __forceinline__ void accumulate_group(const T (&o)[kGroup][4], Acc<T> &acc) {
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            if (sizeof(T) == 8) {
+                acc.add(o[c][v]);
+            } else if (o[c][v] != T(0)) {
+                acc.add(o[c][v]);
+            }
+        }
+}
+
+// Trial bounds; fixed-length trials (off == nullptr) need not be FIXED: their
+// length may not be a multiple of 4 or the IDs may be unaligned.
+template <bool FIXED>
+__device__ __forceinline__ TrialRange fused_range(const YetView &y, const int64_t *__restrict__ off, int64_t i) {
+    if (FIXED || off == nullptr) return TrialRange{i * y.events_per_trial, (i + 1) * y.events_per_trial};
+    return TrialRange{off[i], off[i + 1]};
+}
+
+template <typename T, bool FIXED, bool ALIGNED>
+__global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int64_t *__restrict__ off,
+                                                           const uint32_t *__restrict__ filt, int32_t n_fwords,
+                                                           int32_t fshift, int32_t zero_slot,
+                                                           const T *__restrict__ occ, double agg_ret, double agg_lim,
+                                                           double *__restrict__ ylt) {
     extern __shared__ uint32_t sfilt[];
     for (int i = threadIdx.x; i < n_fwords; i += blockDim.x) sfilt[i] = filt[i];
     __syncthreads();
     const int lane = lane_id();
-    const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t trial = wave; trial < y.n_trials; trial += n_waves) {
-        const TrialRange r = trial_range(y, trial);
+    constexpr int64_t kSpan = (int64_t)kGroup * 4 * kWave;
+    const int64_t last_granule = (y.n_events - 1) & ~3LL;  // launched only with n_events >= 1
+    int64_t trial = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    TrialRange r{0, 0};
+    IdGroup cur;
+    uint32_t cur_valid = 0;
+    if (trial < y.n_trials) {
+        r = fused_range<FIXED>(y, off, trial);
+        cur_valid = load_group<FIXED, ALIGNED>(y, r, chunk_start(y, r.b), lane, last_granule, cur);
+    }
+    while (trial < y.n_trials) {
+        // gathers of this trial first, then the IDs of the next trial, so
+        // that waiting for the gathers does not wait for the prefetch
+        T o[kGroup][4];
+        gather_group<T>(cur, cur_valid, sfilt, fshift, zero_slot, occ, o);
+        // the last round of a wave loads its own last trial again (unused)
+        const int64_t next = trial + n_waves;
+        const int64_t pre = next < y.n_trials ? next : trial;
+        const TrialRange rn = fused_range<FIXED>(y, off, pre);
+        IdGroup nxt;
+        const uint32_t nxt_valid = load_group<FIXED, ALIGNED>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
         Acc<T> acc = Acc<T>::zero();
-        for (int64_t p = chunk_start(y, r.b) + 4 * lane; p < r.e; p += 4 * kWave) {
-            int32_t id[4];
-            load4(y, p, r, id);
-            bool hit[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const uint32_t blk = id[v] >= 0 ? ((uint32_t)id[v] >> fshift) : 0u;
-                hit[v] = id[v] >= 0 && ((sfilt[blk >> 5] >> (blk & 31)) & 1u);
-            }
-            T o[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) o[v] = hit[v] ? occ[id[v]] : T(0);
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                if (hit[v]) acc.add(o[v]);
+        accumulate_group(o, acc);
+        for (int64_t base = chunk_start(y, r.b) + kSpan; base < r.e; base += kSpan) {
+            IdGroup more;
+            const uint32_t mv = load_group<FIXED, ALIGNED>(y, r, base, lane, last_granule, more);
+            gather_group<T>(more, mv, sfilt, fshift, zero_slot, occ, o);
+            accumulate_group(o, acc);
         }
         const double S = wave_allreduce(acc).value();
         if (lane == 0) ylt[trial] = clamp_excess(S, agg_ret, agg_lim);
+        trial = next;
+        r = rn;
+        cur = nxt;
+        cur_valid = nxt_valid;
     }
 }
 
@@ -442,26 +561,31 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
     if (y.n_trials == 0) return hipSuccess;
     const int grid = grid_for_trials(y.n_trials, 4, 8);
     const dim3 blk(256);
-    if (!events && L.layout == kFused) {
+    if (!events && L.layout == kFused && y.n_events > 0) {
         const size_t lds = (size_t)L.tab.n_fwords * sizeof(uint32_t);
-        static bool attr_set[2] = {false, false};
-        const int which = sizeof(T) == 8 ? 0 : 1;
-        if (!attr_set[which]) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_trial_pass_fused<T>),
+        const bool fixed = y.offsets == nullptr && y.aligned16 && y.events_per_trial > 0 && (y.events_per_trial % 4) == 0;
+        auto kern = fixed ? &k_trial_pass_fused<T, true, true>
+                          : (y.aligned16 ? &k_trial_pass_fused<T, false, true> : &k_trial_pass_fused<T, false, false>);
+        const int variant = fixed ? 0 : (y.aligned16 ? 1 : 2);
+        static bool attr_set[2][3] = {};
+        bool &done = attr_set[sizeof(T) == 8 ? 0 : 1][variant];
+        if (!done) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kFilterBits / 8));
             if (e != hipSuccess) return e;
-            attr_set[which] = true;
+            done = true;
         }
         const int per_cu = lds > 80 * 1024 ? 1 : 2;
         const int fgrid = grid_for_trials(y.n_trials, 16, per_cu);
-        hipLaunchKernelGGL((k_trial_pass_fused<T>), dim3(fgrid), dim3(1024), lds, s, y, L.tab.filt, L.tab.n_fwords,
-                           L.tab.fshift, static_cast<const T *>(L.tab.occ), t.agg_ret, t.agg_lim, d_ylt);
+        hipLaunchKernelGGL(kern, dim3(fgrid), dim3(1024), lds, s, y, y.offsets, L.tab.filt, L.tab.n_fwords, L.tab.fshift,
+                           L.catalog, static_cast<const T *>(L.tab.occ), t.agg_ret, t.agg_lim, d_ylt);
         return hipGetLastError();
     }
     if (!events) {
         switch (L.layout) {
             case kDirect: hipLaunchKernelGGL((k_trial_pass<T, kDirect>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt); break;
             case kSparse: hipLaunchKernelGGL((k_trial_pass<T, kSparse>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt); break;
+            case kFused: hipLaunchKernelGGL((k_trial_pass<T, kFused>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt); break;
             default: hipLaunchKernelGGL((k_trial_pass<T, kCompact>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt); break;
         }
     } else {
@@ -504,7 +628,7 @@ hipError_t fuse_t(LayerHost &L, const Terms<T> &t, const void *d_rows, const int
                   hipStream_t s) {
     T *occ = static_cast<T *>(const_cast<void *>(L.tab.occ));
     const int g = cu_count() * 4;
-    hipLaunchKernelGGL((k_fill_zero<T>), dim3(g), dim3(256), 0, s, occ, (int64_t)L.catalog);
+    hipLaunchKernelGGL((k_fill_zero<T>), dim3(g), dim3(256), 0, s, occ, (int64_t)L.catalog + 1);
     if (n_present > 0)
         hipLaunchKernelGGL((k_fuse<T>), dim3(g), dim3(256), 0, s, static_cast<const T *>(d_rows), d_present, n_present,
                            t, occ);

@@ -147,15 +147,20 @@ def test_edge_cases(name, kw, misalign, prec):
 
 
 @pytest.mark.parametrize("K", [0, 1, 3, 7, 256, 1000, 1001])
-def test_fixed_length_trials(K):
+@pytest.mark.parametrize("misalign", [False, True])
+def test_fixed_length_trials(K, misalign):
+    """Trials without an offsets array, of lengths that are and are not
+    multiples of 4, with aligned and unaligned IDs, on every layout."""
     T, C = 257, 2000
     rng = np.random.default_rng(K)
     ids = rng.integers(0, C, size=T * K, dtype=np.int32)
     _, _, spec = W.random_case(41, 1, 1.0, C, 4, 600)
     ref = oracle_run(ids, None, T, C, K, spec)
     for prec in PRECS:
-        y = gpu_layer_run(ids, None, T, C, K, spec, prec, "compact")
-        assert_close_to_oracle(y, ref, prec)
+        ys = [gpu_layer_run(ids, None, T, C, K, spec, prec, lay, ids_misalign=misalign and K > 0)
+              for lay in ("compact", "fused")]
+        assert_close_to_oracle(ys[0], ref, prec)
+        assert np.array_equal(ys[0], ys[1])
 
 
 @pytest.mark.parametrize("prec", PRECS)
