@@ -150,10 +150,34 @@ ara_status ara_run_layer(ara_yet yet, ara_layer layer, double *d_ylt, void *hip_
 ara_status ara_run_layer_events(ara_yet yet, ara_layer layer, double *d_ylt, double *d_event_cum,
                                 double *d_event_net, void *hip_stream);
 
-/* Several layers over one YET in one launch (Algorithm 1's loop over the
- * layers of a program): d_ylts[l] receives layer l's YLT (binary64
- * [n_trials], caller-owned).  Each layer's YLT is bitwise the one
- * ara_run_layer gives for it.  Asynchronous. */
+/* Several layers over one YET in one pass (Algorithm 1's loop over the
+ * layers of a program, with the YET read once for all of them).
+ *
+ * A batch holds, for every catalogue event, one 64-byte (FP64) or 32-byte
+ * (FP32C) record of the layers in which its occurrence loss is non-zero and
+ * those losses; the trial pass reads one record per trial-event and keeps one
+ * running sum per (layer, lane), adding each layer's losses in the same order
+ * as the single-layer pass.
+ *   layers    1 .. ARA_MAX_BATCH layer handles, all built against this YET
+ *             with ARA_LAYOUT_FUSED (or AUTO) and the same precision
+ *             (else ARA_ERR_UNSUPPORTED / ARA_ERR_INVALID_ARG).  The batch
+ *             copies what it needs: the layers may be destroyed afterwards.
+ * ara_create_batch is synchronous; the batch owns its device memory.
+ * ara_run_batch writes d_ylts[l] (binary64 [n_trials], caller-owned) for
+ * every layer l of the batch; each is bitwise the YLT ara_run_layer gives
+ * for that layer.  The launch is replayed from a HIP graph captured on the
+ * first run.  Asynchronous on hip_stream. */
+#define ARA_MAX_BATCH 64
+typedef struct ara_batch_s *ara_batch;
+ara_status ara_create_batch(ara_yet yet, const ara_layer *layers, int32_t n_layers, ara_batch *out);
+ara_status ara_run_batch(ara_batch batch, double *const *d_ylts, void *hip_stream);
+size_t ara_batch_device_bytes(ara_batch batch);
+/* Launch shape chosen for the batch (0, 0 before its first run). */
+ara_status ara_batch_launch_config(ara_batch batch, int32_t *threads, int32_t *wg_per_cu);
+void ara_destroy_batch(ara_batch batch);
+
+/* One-shot form: ara_create_batch + ara_run_batch + ara_destroy_batch
+ * (synchronous; n_layers up to ARA_MAX_BATCH). */
 ara_status ara_run_layers(ara_yet yet, const ara_layer *layers, double *const *d_ylts, int32_t n_layers,
                           void *hip_stream);
 

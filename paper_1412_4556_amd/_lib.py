@@ -25,6 +25,7 @@ ERRORS = {
 ARA_FP64, ARA_FP32C = 0, 1
 ARA_LAYOUT_AUTO, ARA_LAYOUT_DIRECT, ARA_LAYOUT_SPARSE, ARA_LAYOUT_COMPACT, ARA_LAYOUT_FUSED = 0, 1, 2, 3, 4
 ARA_MAX_ELTS = 32
+ARA_MAX_BATCH = 64
 
 _P = ctypes.c_void_p
 _I32, _I64, _D, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -36,6 +37,11 @@ SIGNATURES = {
     "ara_run_layer": (_I32, [_P, _P, _P, _P]),
     "ara_run_layer_events": (_I32, [_P, _P, _P, _P, _P, _P]),
     "ara_run_layers": (_I32, [_P, _P, _P, _I32, _P]),
+    "ara_create_batch": (_I32, [_P, _P, _I32, _P]),
+    "ara_run_batch": (_I32, [_P, _P, _P]),
+    "ara_batch_device_bytes": (_SZ, [_P]),
+    "ara_batch_launch_config": (_I32, [_P, _P, _P]),
+    "ara_destroy_batch": (None, [_P]),
     "ara_pml_tvar": (_I32, [_P, _I64, _P, _I32, _P, _P, _P]),
     "ara_layer_device_bytes": (_SZ, [_P]),
     "ara_layer_layout": (_I32, [_P]),

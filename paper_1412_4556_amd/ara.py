@@ -143,8 +143,58 @@ def run_layer_events(yet: Yet, layer: Layer, want_cum: bool = True, want_net: bo
     return ylt, cum, net
 
 
+class Batch:
+    """Several fused layers prepared for one pass over the YET."""
+
+    def __init__(self, yet: Yet, layers: Sequence[Layer]):
+        n = len(layers)
+        hs = (ctypes.c_void_p * n)(*[l.handle.value for l in layers])
+        h = ctypes.c_void_p()
+        L.check(L.lib().ara_create_batch(yet.handle, hs, n, ctypes.byref(h)))
+        self._h = h
+        self.yet = yet
+        self.n_layers = n
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def device_bytes(self) -> int:
+        return int(L.lib().ara_batch_device_bytes(self._h))
+
+    @property
+    def launch_config(self):
+        t, w = ctypes.c_int32(), ctypes.c_int32()
+        L.check(L.lib().ara_batch_launch_config(self._h, ctypes.byref(t), ctypes.byref(w)))
+        return int(t.value), int(w.value)
+
+    def run(self, outs: Optional[Sequence[torch.Tensor]] = None, stream=None):
+        if outs is None:
+            outs = [torch.empty(self.yet.n_trials, dtype=torch.float64, device=self.yet.event_ids.device)
+                    for _ in range(self.n_layers)]
+        if len(outs) != self.n_layers:
+            raise ValueError("one output tensor per layer")
+        for o in outs:
+            _check_out(o, self.yet.n_trials, "outs[i]")
+        ps = (ctypes.c_void_p * self.n_layers)(*[o.data_ptr() for o in outs])
+        L.check(L.lib().ara_run_batch(self._h, ps, ctypes.c_void_p(_stream(stream))))
+        return list(outs)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().ara_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def run_layers(yet: Yet, layers: Sequence[Layer], outs: Optional[Sequence[torch.Tensor]] = None, stream=None):
-    """YLTs of several layers in one launch."""
+    """YLTs of several layers in one pass (one-shot batch; synchronous)."""
     n = len(layers)
     if outs is None:
         outs = [torch.empty(yet.n_trials, dtype=torch.float64, device=yet.event_ids.device) for _ in range(n)]

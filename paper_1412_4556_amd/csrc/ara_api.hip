@@ -3,7 +3,11 @@
 // ara_kernels.hip and ara_select.hip.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <limits>
 #include <new>
@@ -21,6 +25,25 @@ struct ara_yet_s {
 
 struct ara_layer_s {
     ara::LayerHost h;
+    int device = 0;
+};
+
+struct ara_batch_s {
+    ara::YetView yv{};
+    int32_t n = 0;
+    int32_t precision = 0;
+    int32_t catalog = 0;
+    void *d_rec = nullptr;
+    void *d_ovf_lid = nullptr;
+    void *d_ovf_val = nullptr;
+    double **d_ylts = nullptr;  // device array of the YLT pointers of the last run
+    double *d_agg = nullptr;    // [2n]: aggregate retentions, then limits
+    std::vector<double *> h_ylts;
+    ara::BatchLaunch cfg{256, 1};
+    bool tuned = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    size_t bytes = 0;
     int device = 0;
 };
 
@@ -384,14 +407,239 @@ ara_status ara_run_layer_events(ara_yet yet, ara_layer layer, double *d_ylt, dou
     return ARA_OK;
 }
 
+static void free_batch(ara_batch b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (void *p : {b->d_rec, b->d_ovf_lid, b->d_ovf_val, (void *)b->d_ylts, (void *)b->d_agg})
+        if (p) (void)hipFree(p);
+    delete b;
+}
+
+ara_status ara_create_batch(ara_yet yet, const ara_layer *layers, int32_t n_layers, ara_batch *out) {
+    if (!out) return fail(ARA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!yet || !layers) return fail(ARA_ERR_INVALID_ARG, "NULL yet or layers");
+    if (n_layers < 1) return fail(ARA_ERR_INVALID_ARG, "n_layers < 1");
+    if (n_layers > ARA_MAX_BATCH) return fail(ARA_ERR_UNSUPPORTED, "n_layers exceeds ARA_MAX_BATCH");
+    const void *occ[ARA_MAX_BATCH];
+    int32_t prec = -1;
+    for (int l = 0; l < n_layers; ++l) {
+        if (!layers[l]) return fail(ARA_ERR_INVALID_ARG, "NULL layer handle");
+        const ara::LayerHost &h = layers[l]->h;
+        if (h.catalog != yet->catalog) return fail(ARA_ERR_INVALID_ARG, "layer built for another catalogue");
+        if (h.layout != ara::kFused) return fail(ARA_ERR_UNSUPPORTED, "batched layers must use the fused layout");
+        if (prec >= 0 && h.precision != prec) return fail(ARA_ERR_INVALID_ARG, "layers of different precisions");
+        prec = h.precision;
+        occ[l] = h.tab.occ;
+    }
+    ara_batch_s *b = new (std::nothrow) ara_batch_s;
+    if (!b) return fail(ARA_ERR_OOM, "host allocation");
+    b->yv = yet->v;
+    b->n = n_layers;
+    b->precision = prec;
+    b->catalog = yet->catalog;
+    (void)hipGetDevice(&b->device);
+    const bool fp64 = prec == ARA_FP64;
+    const size_t rec_bytes = fp64 ? 64 : 32, val_bytes = fp64 ? 8 : 4;
+    const size_t C = (size_t)yet->catalog;
+    hipStream_t s = ara::internal_stream();
+    int32_t *d_count = nullptr;
+    unsigned long long *d_ctr = nullptr;  // [0] overflow total, [1] fill cursor
+    unsigned long long h_ctr[2] = {0, 0};
+    hipError_t e = dev_alloc(reinterpret_cast<void **>(&d_count), C * sizeof(int32_t));
+    if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&d_ctr), sizeof(h_ctr));
+    if (e == hipSuccess) e = hipMemcpyAsync(d_ctr, h_ctr, sizeof(h_ctr), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = ara::launch_batch_count(occ, n_layers, yet->catalog, fp64, d_count, d_ctr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_ctr, d_ctr, sizeof(h_ctr), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    const unsigned long long n_ovf = h_ctr[0];
+    if (e == hipSuccess && n_ovf >= (1ULL << 32)) e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = dev_alloc(&b->d_rec, C * rec_bytes);
+    if (e == hipSuccess) e = dev_alloc(&b->d_ovf_lid, (size_t)n_ovf);
+    if (e == hipSuccess) e = dev_alloc(&b->d_ovf_val, (size_t)n_ovf * val_bytes);
+    if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_ylts), sizeof(double *) * n_layers);
+    if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_agg), sizeof(double) * 2 * n_layers);
+    std::vector<double> agg(2 * n_layers);
+    for (int l = 0; l < n_layers; ++l) {
+        agg[l] = layers[l]->h.t64.agg_ret;
+        agg[n_layers + l] = layers[l]->h.t64.agg_lim;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_agg, agg.data(), sizeof(double) * agg.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = ara::launch_batch_fill(occ, n_layers, yet->catalog, fp64, d_count, b->d_rec,
+                                   static_cast<uint8_t *>(b->d_ovf_lid), b->d_ovf_val, d_ctr + 1, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (d_count) (void)hipFree(d_count);
+    if (d_ctr) (void)hipFree(d_ctr);
+    if (e != hipSuccess) {
+        free_batch(b);
+        return hip_fail(e, "building the batch records");
+    }
+    b->bytes = C * rec_bytes + (size_t)n_ovf * (1 + val_bytes) + sizeof(double *) * n_layers +
+               sizeof(double) * 2 * n_layers;
+    b->h_ylts.assign(n_layers, nullptr);
+    *out = b;
+    return ARA_OK;
+}
+
+void ara_destroy_batch(ara_batch batch) {
+    if (!batch) return;
+    (void)hipDeviceSynchronize();
+    free_batch(batch);
+}
+
+size_t ara_batch_device_bytes(ara_batch batch) { return batch ? batch->bytes : 0; }
+
+namespace {
+
+ara::BatchTables batch_tables(ara_batch b) {
+    ara::BatchTables t{};
+    t.rec = b->d_rec;
+    t.ovf_lid = static_cast<const uint8_t *>(b->d_ovf_lid);
+    t.ovf_val = b->d_ovf_val;
+    t.ylts = b->d_ylts;
+    t.agg_ret = b->d_agg;
+    t.agg_lim = b->d_agg + b->n;
+    t.n_layers = b->n;
+    return t;
+}
+
+// Launch shapes are chosen by timing the real pass once per (precision,
+// layers, trial count, YET form) and remembered for the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int64_t, int, int>, ara::BatchLaunch> g_tuned;
+
+hipError_t tune_batch(ara_batch b, hipStream_t s) {
+    const bool fp64 = b->precision == ARA_FP64;
+    const int form = b->yv.offsets ? 1 : 0;
+    const auto key = std::make_tuple(b->precision, b->n, b->yv.n_trials, form, (int)b->yv.aligned16);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            b->cfg = it->second;
+            b->tuned = true;
+            return hipSuccess;
+        }
+    }
+    const char *force = std::getenv("ARA_BATCH_LAUNCH");  // "threads,wg_per_cu" skips the search
+    std::vector<ara::BatchLaunch> cands;
+    if (force) {
+        int t = 256, w = 1;
+        if (std::sscanf(force, "%d,%d", &t, &w) == 2 && t >= 64 && t <= 512 && t % 64 == 0 && w >= 1) cands.push_back({t, w});
+    }
+    if (cands.empty())
+        for (int t : {128, 256, 512})
+            for (int w : {1, 2, 4, 8})
+                if (ara::batch_lds_bytes(b->n, t) * (size_t)w <= 160u * 1024u) cands.push_back({t, w});
+    if (cands.empty()) cands.push_back({64, 1});
+    const ara::BatchTables tb = batch_tables(b);
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = 1e30f;
+    ara::BatchLaunch best_cfg = cands[0];
+    for (const auto &c : cands) {
+        if (e != hipSuccess) break;
+        if (cands.size() > 1) e = ara::launch_batch_pass(b->yv, tb, fp64, c, s);  // warm-up
+        float tot = 0.0f;
+        for (int rep = 0; rep < 2 && e == hipSuccess && cands.size() > 1; ++rep) {
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = ara::launch_batch_pass(b->yv, tb, fp64, c, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            tot += ms;
+        }
+        if (e == hipSuccess && tot < best) {
+            best = tot;
+            best_cfg = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    b->cfg = best_cfg;
+    b->tuned = true;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuned[key] = best_cfg;
+    return hipSuccess;
+}
+
+hipError_t capture_batch(ara_batch b) {
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = ara::launch_batch_pass(b->yv, batch_tables(b), b->precision == ARA_FP64, b->cfg, cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = le;
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) b->graph = g;
+        else if (g) (void)hipGraphDestroy(g);
+    }
+    (void)hipStreamDestroy(cs);
+    return e;
+}
+
+}  // namespace
+
+ara_status ara_run_batch(ara_batch batch, double *const *d_ylts, void *hip_stream) {
+    if (!batch || !d_ylts) return fail(ARA_ERR_INVALID_ARG, "NULL batch or d_ylts");
+    for (int l = 0; l < batch->n; ++l)
+        if (!d_ylts[l] && batch->yv.n_trials > 0) return fail(ARA_ERR_INVALID_ARG, "NULL YLT pointer");
+    if (batch->yv.n_trials == 0) return ARA_OK;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipSuccess;
+    if (!std::equal(batch->h_ylts.begin(), batch->h_ylts.end(), d_ylts)) {
+        for (int l = 0; l < batch->n; ++l) batch->h_ylts[l] = d_ylts[l];
+        e = hipMemcpyAsync(batch->d_ylts, batch->h_ylts.data(), sizeof(double *) * batch->n, hipMemcpyHostToDevice,
+                           s);
+        if (e != hipSuccess) return hip_fail(e, "copy of the YLT pointers");
+    }
+    if (batch->yv.n_events == 0) {
+        // every trial is empty, and an empty trial's year loss is
+        // min(max(0 - FT3_1, 0), FT3_2) = 0 since FT3_1 >= 0
+        for (int l = 0; l < batch->n && e == hipSuccess; ++l)
+            e = ara::launch_fill_zero(d_ylts[l], batch->yv.n_trials, s);
+        if (e != hipSuccess) return hip_fail(e, "zero YLTs");
+        return ARA_OK;
+    }
+    if (!batch->tuned) {
+        e = tune_batch(batch, s);
+        if (e != hipSuccess) return hip_fail(e, "batch launch tuning");
+    }
+    if (!batch->exec) {
+        e = capture_batch(batch);
+        if (e != hipSuccess) return hip_fail(e, "batch graph capture");
+    }
+    e = hipGraphLaunch(batch->exec, s);
+    if (e != hipSuccess) return hip_fail(e, "batch graph launch");
+    return ARA_OK;
+}
+
+ara_status ara_batch_launch_config(ara_batch batch, int32_t *threads, int32_t *wg_per_cu) {
+    if (!batch || !threads || !wg_per_cu) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    *threads = batch->tuned ? batch->cfg.threads : 0;
+    *wg_per_cu = batch->tuned ? batch->cfg.wg_per_cu : 0;
+    return ARA_OK;
+}
+
 ara_status ara_run_layers(ara_yet yet, const ara_layer *layers, double *const *d_ylts, int32_t n_layers,
                           void *hip_stream) {
-    (void)yet;
-    (void)layers;
-    (void)d_ylts;
-    (void)n_layers;
-    (void)hip_stream;
-    return fail(ARA_ERR_UNSUPPORTED, "ara_run_layers is not built yet");
+    ara_batch b = nullptr;
+    ara_status st = ara_create_batch(yet, layers, n_layers, &b);
+    if (st != ARA_OK) return st;
+    st = ara_run_batch(b, d_ylts, hip_stream);
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
+    ara_destroy_batch(b);
+    if (st != ARA_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "batched pass");
+    return ARA_OK;
 }
 
 ara_status ara_pml_tvar(const double *d_ylt, int64_t n_trials, const double *h_return_periods, int32_t n_rp,

@@ -92,9 +92,51 @@ hipError_t launch_validate_yet(const YetView &y, int32_t catalog, int32_t *d_fla
 hipError_t launch_trial_pass(const YetView &y, const LayerHost &L, double *d_ylt, hipStream_t s);
 hipError_t launch_trial_pass_events(const YetView &y, const LayerHost &L, double *d_ylt, double *d_cum,
                                     double *d_net, hipStream_t s);
-hipError_t launch_trial_pass_multi(const YetView &y, const LayerHost *const *layers, double *const *ylts,
-                                   int32_t n_layers, hipStream_t s, void *d_scratch, size_t scratch_bytes);
-size_t multi_scratch_bytes(int32_t n_layers);
+
+// Batched pass (ara_kernels.hip).  Records: one per catalogue event, bytes
+// 0..7 the layer indices of its entries (kNoLayer = empty), then kRecVals
+// values.  An event with more entries than fit keeps kRecVals - 1 inline,
+// marks byte 7 with kOverflowMark, holds the number of further entries in
+// byte kRecVals - 1 and their start in the overflow arrays in value slot
+// kRecVals - 1 (as a uint32).
+constexpr uint8_t kNoLayer = 0xff, kOverflowMark = 0xfe;
+template <typename T>
+struct RecFormat;
+template <>
+struct RecFormat<double> {
+    static constexpr int kVals = 7, kBytes = 64;
+};
+template <>
+struct RecFormat<float> {
+    static constexpr int kVals = 6, kBytes = 32;
+};
+
+struct BatchTables {
+    const void *rec;          // [catalog] records
+    const uint8_t *ovf_lid;   // overflow layer indices
+    const void *ovf_val;      // overflow values
+    double *const *ylts;      // device array [n_layers] of YLT pointers
+    const double *agg_ret;    // [n_layers]
+    const double *agg_lim;    // [n_layers]
+    int32_t n_layers;
+};
+
+struct BatchLaunch {
+    int threads;     // work-group size (multiple of 64)
+    int wg_per_cu;   // work-groups per CU requested (clamped by LDS)
+};
+
+// occ pointers of the layers -> records.  Returns the total number of
+// overflow entries through *d_ovf_total (device) in the counting phase.
+hipError_t launch_batch_count(const void *const *occ, int32_t n_layers, int32_t catalog, bool fp64, int32_t *d_count,
+                              unsigned long long *d_ovf_total, hipStream_t s);
+hipError_t launch_batch_fill(const void *const *occ, int32_t n_layers, int32_t catalog, bool fp64,
+                             const int32_t *d_count, void *d_rec, uint8_t *d_ovf_lid, void *d_ovf_val,
+                             unsigned long long *d_ovf_cursor, hipStream_t s);
+hipError_t launch_batch_pass(const YetView &y, const BatchTables &b, bool fp64, const BatchLaunch &cfg, hipStream_t s);
+size_t batch_lds_bytes(int32_t n_layers, int threads);
+// d[0 .. n) = 0 with a kernel (no memset node if the caller captures a graph)
+hipError_t launch_fill_zero(double *d, int64_t n, hipStream_t s);
 
 // Selection (ara_select.hip): PML / TVaR for n_rp tail sizes k[r].
 hipError_t pml_tvar_device(const double *d_ylt, int64_t n, const int64_t *h_k, int32_t n_rp, double *h_pml,

@@ -481,6 +481,179 @@ __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int6
     }
 }
 
+// --------------------------------------------------------------------------------------------
+// batched pass: many layers, one read of the YET
+
+template <typename T>
+struct alignas(RecFormat<T>::kBytes) Record {
+    uint8_t lid[8];
+    T val[RecFormat<T>::kVals];
+};
+static_assert(sizeof(Record<double>) == 64 && sizeof(Record<float>) == 32, "record size");
+
+struct OccPtrs {
+    const void *p[ARA_MAX_BATCH];
+};
+
+template <typename T>
+__global__ void k_batch_count(OccPtrs occ, int32_t n_layers, int32_t catalog, int32_t *__restrict__ count,
+                              unsigned long long *ovf_total) {
+    constexpr int KV = RecFormat<T>::kVals;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < catalog; e += (int64_t)gridDim.x * blockDim.x) {
+        int n = 0;
+        for (int l = 0; l < n_layers; ++l) n += static_cast<const T *>(occ.p[l])[e] != T(0);
+        count[e] = n;
+        if (n > KV) atomicAdd(ovf_total, (unsigned long long)(n - (KV - 1)));
+    }
+}
+
+template <typename T>
+__global__ void k_batch_fill(OccPtrs occ, int32_t n_layers, int32_t catalog, const int32_t *__restrict__ count,
+                             Record<T> *__restrict__ rec, uint8_t *__restrict__ ovf_lid, T *__restrict__ ovf_val,
+                             unsigned long long *cursor) {
+    constexpr int KV = RecFormat<T>::kVals;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < catalog; e += (int64_t)gridDim.x * blockDim.x) {
+        Record<T> r;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) r.lid[k] = kNoLayer;
+#pragma unroll
+        for (int k = 0; k < KV; ++k) r.val[k] = T(0);
+        const int n = count[e];
+        const bool ovf = n > KV;
+        const int n_in = ovf ? KV - 1 : KV;
+        unsigned long long pos = 0;
+        if (ovf) pos = atomicAdd(cursor, (unsigned long long)(n - n_in));
+        int k = 0;
+        for (int l = 0; l < n_layers; ++l) {
+            const T v = static_cast<const T *>(occ.p[l])[e];
+            if (v == T(0)) continue;
+            if (k < n_in) {
+                r.lid[k] = (uint8_t)l;
+                r.val[k] = v;
+            } else {
+                ovf_lid[pos + (k - n_in)] = (uint8_t)l;
+                ovf_val[pos + (k - n_in)] = v;
+            }
+            ++k;
+        }
+        if (ovf) {
+            r.lid[7] = kOverflowMark;
+            r.lid[KV - 1] = (uint8_t)(n - n_in);
+            const uint32_t p32 = (uint32_t)pos;
+            __builtin_memcpy(&r.val[KV - 1], &p32, sizeof(p32));
+        }
+        rec[e] = r;
+    }
+}
+
+// Row stride of the per-wave accumulator table acc[layer][lane] (one spare
+// slot per row keeps the epilogue's row reads off a single LDS bank).
+constexpr int kAccStride = kWave + 1;
+
+template <typename T>
+__device__ __forceinline__ void acc_add(Acc<T> *acc, uint32_t l, int lane, T v) {
+    Acc<T> a = acc[l * kAccStride + lane];
+    a.add(v);
+    acc[l * kAccStride + lane] = a;
+}
+
+template <typename T>
+__device__ __forceinline__ void add_record(const Record<T> &r, bool valid, Acc<T> *acc, int lane,
+                                           const BatchTables &b) {
+    constexpr int KV = RecFormat<T>::kVals;
+    if (!valid) return;
+    const bool ovf = r.lid[7] == kOverflowMark;
+    const int n_in = ovf ? KV - 1 : KV;
+#pragma unroll
+    for (int k = 0; k < KV; ++k)
+        if (k < n_in && r.lid[k] != kNoLayer) acc_add(acc, r.lid[k], lane, r.val[k]);
+    if (ovf) {
+        uint32_t pos;
+        __builtin_memcpy(&pos, &r.val[KV - 1], sizeof(pos));
+        const int cnt = r.lid[KV - 1];
+        const T *ov = static_cast<const T *>(b.ovf_val);
+        for (int i = 0; i < cnt; ++i) acc_add(acc, b.ovf_lid[pos + i], lane, ov[pos + i]);
+    }
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave per trial (same lane-to-event mapping and per-lane order as the
+// single-layer passes).  Every record entry (layer l, loss o) of an event
+// handled by lane i is added to acc[l][i]; at the end of the trial lane l
+// folds row l with the butterfly order of wave_allreduce, so layer l's YLT is
+// bitwise the one of its own pass.
+template <typename T, bool FIXED, bool ALIGNED>
+__global__ __launch_bounds__(512) void k_trial_pass_batch(YetView y, const int64_t *__restrict__ off, BatchTables b) {
+    extern __shared__ uint64_t lds_raw[];
+    const int lane = lane_id();
+    const int n_layers = b.n_layers;
+    Acc<T> *acc = reinterpret_cast<Acc<T> *>(lds_raw) + (size_t)(threadIdx.x >> 6) * n_layers * kAccStride;
+    const Record<T> *__restrict__ rec = static_cast<const Record<T> *>(b.rec);
+    double *my_ylt = nullptr;
+    double my_ret = 0.0, my_lim = 0.0;
+    if (lane < n_layers) {
+        my_ylt = b.ylts[lane];
+        my_ret = b.agg_ret[lane];
+        my_lim = b.agg_lim[lane];
+    }
+    for (int l = 0; l < n_layers; ++l) acc[l * kAccStride + lane] = Acc<T>::zero();
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    constexpr int64_t kSpan = (int64_t)kGroup * 4 * kWave;
+    const int64_t last_granule = (y.n_events - 1) & ~3LL;  // launched only with n_events >= 1
+    int64_t trial = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    TrialRange r{0, 0};
+    IdGroup cur;
+    uint32_t cur_valid = 0;
+    if (trial < y.n_trials) {
+        r = fused_range<FIXED>(y, off, trial);
+        cur_valid = load_group<FIXED, ALIGNED>(y, r, chunk_start(y, r.b), lane, last_granule, cur);
+    }
+    while (trial < y.n_trials) {
+        const int64_t next = trial + n_waves;
+        const TrialRange rn = fused_range<FIXED>(y, off, next < y.n_trials ? next : trial);
+        IdGroup nxt;
+        const uint32_t nxt_valid = load_group<FIXED, ALIGNED>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
+        int64_t base = chunk_start(y, r.b);
+        IdGroup g = cur;
+        uint32_t valid = cur_valid;
+        while (true) {
+#pragma unroll
+            for (int c = 0; c < kGroup; ++c) {
+                Record<T> rr[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) rr[v] = rec[g.id[c][v]];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) add_record(rr[v], ((valid >> (4 * c + v)) & 1u) != 0u, acc, lane, b);
+            }
+            base += kSpan;
+            if (base >= r.e) break;
+            valid = load_group<FIXED, ALIGNED>(y, r, base, lane, last_granule, g);
+        }
+        wave_lds_fence();
+        if (lane < n_layers) {
+            const Acc<T> *row = acc + lane * kAccStride;
+            Acc<T> v[kWave / 2];
+#pragma unroll
+            for (int i = 0; i < kWave / 2; ++i) v[i] = Acc<T>::combine(row[i], row[i + kWave / 2]);
+#pragma unroll
+            for (int m = kWave / 4; m >= 1; m >>= 1)
+#pragma unroll
+                for (int i = 0; i < m; ++i) v[i] = Acc<T>::combine(v[i], v[i + m]);
+            my_ylt[trial] = clamp_excess(v[0].value(), my_ret, my_lim);
+        }
+        wave_lds_fence();
+        for (int l = 0; l < n_layers; ++l) acc[l * kAccStride + lane] = Acc<T>::zero();
+        trial = next;
+        r = rn;
+        cur = nxt;
+        cur_valid = nxt_valid;
+    }
+}
+
 template <typename T>
 __global__ void k_fill_zero(T *p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -659,6 +832,76 @@ hipError_t launch_trial_pass_events(const YetView &y, const LayerHost &L, double
                                     double *d_net, hipStream_t s) {
     if (L.precision == ARA_FP32C) return launch_pass_t<float>(y, L, L.t32, d_ylt, d_cum, d_net, true, s);
     return launch_pass_t<double>(y, L, L.t64, d_ylt, d_cum, d_net, true, s);
+}
+
+namespace {
+template <typename T>
+hipError_t batch_count_t(const void *const *occ, int32_t n, int32_t catalog, int32_t *cnt, unsigned long long *tot,
+                         hipStream_t s) {
+    OccPtrs o{};
+    for (int l = 0; l < n; ++l) o.p[l] = occ[l];
+    hipLaunchKernelGGL((k_batch_count<T>), dim3(cu_count() * 4), dim3(256), 0, s, o, n, catalog, cnt, tot);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t batch_fill_t(const void *const *occ, int32_t n, int32_t catalog, const int32_t *cnt, void *rec,
+                        uint8_t *ovf_lid, void *ovf_val, unsigned long long *cursor, hipStream_t s) {
+    OccPtrs o{};
+    for (int l = 0; l < n; ++l) o.p[l] = occ[l];
+    hipLaunchKernelGGL((k_batch_fill<T>), dim3(cu_count() * 4), dim3(256), 0, s, o, n, catalog, cnt,
+                       static_cast<Record<T> *>(rec), ovf_lid, static_cast<T *>(ovf_val), cursor);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t batch_pass_t(const YetView &y, const BatchTables &b, const BatchLaunch &cfg, hipStream_t s) {
+    if (y.n_trials == 0) return hipSuccess;
+    const bool fixed = y.offsets == nullptr && y.aligned16 && y.events_per_trial > 0 && (y.events_per_trial % 4) == 0;
+    auto kern = fixed ? &k_trial_pass_batch<T, true, true>
+                      : (y.aligned16 ? &k_trial_pass_batch<T, false, true> : &k_trial_pass_batch<T, false, false>);
+    const size_t lds = batch_lds_bytes(b.n_layers, cfg.threads);
+    if (lds > 160u * 1024u || cfg.threads < kWave || cfg.threads > 512 || cfg.threads % kWave) return hipErrorInvalidValue;
+    static bool attr_set[2][3] = {};
+    bool &done = attr_set[sizeof(T) == 8 ? 0 : 1][fixed ? 0 : (y.aligned16 ? 1 : 2)];
+    if (!done) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        done = true;
+    }
+    int per_cu = (int)((160 * 1024) / (lds ? lds : 1));
+    if (per_cu > cfg.wg_per_cu) per_cu = cfg.wg_per_cu;
+    if (per_cu < 1) per_cu = 1;
+    const int grid = grid_for_trials(y.n_trials, cfg.threads / kWave, per_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(cfg.threads), lds, s, y, y.offsets, b);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fill_zero<double>), dim3(cu_count() * 4), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+size_t batch_lds_bytes(int32_t n_layers, int threads) {
+    return (size_t)(threads / kWave) * (size_t)n_layers * kAccStride * 8u;
+}
+
+hipError_t launch_batch_count(const void *const *occ, int32_t n_layers, int32_t catalog, bool fp64, int32_t *d_count,
+                              unsigned long long *d_ovf_total, hipStream_t s) {
+    return fp64 ? batch_count_t<double>(occ, n_layers, catalog, d_count, d_ovf_total, s)
+                : batch_count_t<float>(occ, n_layers, catalog, d_count, d_ovf_total, s);
+}
+
+hipError_t launch_batch_fill(const void *const *occ, int32_t n_layers, int32_t catalog, bool fp64,
+                             const int32_t *d_count, void *d_rec, uint8_t *d_ovf_lid, void *d_ovf_val,
+                             unsigned long long *d_ovf_cursor, hipStream_t s) {
+    return fp64 ? batch_fill_t<double>(occ, n_layers, catalog, d_count, d_rec, d_ovf_lid, d_ovf_val, d_ovf_cursor, s)
+                : batch_fill_t<float>(occ, n_layers, catalog, d_count, d_rec, d_ovf_lid, d_ovf_val, d_ovf_cursor, s);
+}
+
+hipError_t launch_batch_pass(const YetView &y, const BatchTables &b, bool fp64, const BatchLaunch &cfg, hipStream_t s) {
+    return fp64 ? batch_pass_t<double>(y, b, cfg, s) : batch_pass_t<float>(y, b, cfg, s);
 }
 
 }  // namespace ara

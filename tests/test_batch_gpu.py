@@ -1,0 +1,129 @@
+"""Batched pass: many layers over one YET in one launch.
+
+Every layer's YLT from the batch must be bitwise the one of its own
+single-layer pass, and within tolerance of the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_cases import TOL, assert_close_to_oracle, oracle_run
+from paper_1412_4556_amd import _lib as L
+from paper_1412_4556_amd import ara as A
+from paper_1412_4556_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _layers(seed, n, C, max_j, elt_size):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        J = int(rng.integers(1, max_j + 1))
+        _, _, spec = W.random_case(seed * 1000 + i, 1, 1.0, C, J, elt_size)
+        out.append(spec)
+    return out
+
+
+def _yet(ids, off, T, C, K=0, misalign=False):
+    if misalign:
+        buf = torch.empty(len(ids) + 1, dtype=torch.int32, device="cuda")
+        buf[1:] = torch.from_numpy(np.ascontiguousarray(ids, np.int32)).cuda()
+        t_ids = buf[1:]
+    else:
+        t_ids = torch.from_numpy(np.ascontiguousarray(ids, np.int32)).cuda()
+    t_off = None if off is None else torch.from_numpy(np.ascontiguousarray(off, np.int64)).cuda()
+    return A.Yet(t_ids, t_off, T, C, K)
+
+
+CASES = [
+    # name, trials, mean_len, catalog, n_layers, max_elts, elt_size, fixed_len, misalign
+    ("poisson_12", 3000, 200.0, 20000, 12, 8, 3000, False, False),
+    ("poisson_64", 2000, 300.0, 50000, 64, 6, 4000, False, False),
+    ("fixed_1000", 600, 1000, 30000, 9, 5, 5000, True, False),
+    ("fixed_7_misaligned", 700, 7, 3000, 5, 4, 600, True, True),
+    ("empties", 1500, 20.0, 5000, 7, 3, 800, False, False),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_batch_equals_single_layer_passes(case, prec):
+    name, T, L_, C, n, max_j, esz, fixed, mis = case
+    if fixed:
+        rng = np.random.default_rng(T)
+        K = int(L_)
+        ids = rng.integers(0, C, size=T * K, dtype=np.int32)
+        off = None
+    else:
+        K = 0
+        ids, off, _ = W.random_case(T, T, L_, C, 1, 1, empty_frac=0.2 if name == "empties" else 0.0)
+    specs = _layers(hash(name) % 1000, n, C, max_j, esz)
+    yet = _yet(ids, off, T, C, K, mis)
+    layers = [A.Layer(yet, s, prec, "fused") for s in specs]
+    singles = [A.run_layer(yet, l).cpu().numpy() for l in layers]
+    batch = A.Batch(yet, layers)
+    outs = batch.run()
+    torch.cuda.synchronize()
+    threads, per_cu = batch.launch_config
+    assert threads % 64 == 0 and per_cu >= 1
+    for l in range(n):
+        assert np.array_equal(outs[l].cpu().numpy(), singles[l]), (name, l)
+    # a second run (graph replay) into new buffers gives the same bits
+    outs2 = batch.run()
+    torch.cuda.synchronize()
+    for l in range(n):
+        assert np.array_equal(outs2[l].cpu().numpy(), singles[l])
+    # oracle on a few layers
+    for l in (0, n // 2, n - 1):
+        ref = oracle_run(ids, off, T, C, K, specs[l])
+        assert_close_to_oracle(singles[l], ref, prec)
+
+
+def test_batch_overflow_records():
+    """Dense ELTs over a small catalogue: most events sit in more layers than a
+    record holds inline, so the overflow entries carry most of the losses."""
+    T, C = 800, 500
+    ids, off, _ = W.random_case(77, T, 60.0, C, 1, 1)
+    specs = []
+    for i in range(64):
+        _, _, s = W.random_case(900 + i, 1, 1.0, C, 1, 400, terms="open", integer_losses=True)
+        specs.append(s)
+    yet = _yet(ids, off, T, C)
+    for prec in ("fp64", "fp32c"):
+        layers = [A.Layer(yet, s, prec, "fused") for s in specs]
+        outs = A.run_layers(yet, layers)
+        for l in (0, 13, 63):
+            ref = oracle_run(ids, off, T, C, 0, specs[l])
+            assert np.array_equal(outs[l].cpu().numpy(), ref["ylt"])  # integer losses: exact
+        for l in range(64):
+            assert np.array_equal(outs[l].cpu().numpy(), A.run_layer(yet, layers[l]).cpu().numpy())
+
+
+def test_batch_errors():
+    ids, off, spec = W.random_case(5, 100, 10.0, 1000, 2, 200)
+    yet = _yet(ids, off, 100, 1000)
+    fused = A.Layer(yet, spec, "fp64", "fused")
+    compact = A.Layer(yet, spec, "fp64", "compact")
+    f32 = A.Layer(yet, spec, "fp32c", "fused")
+    with pytest.raises(L.AraError) as ei:
+        A.Batch(yet, [fused, compact])
+    assert ei.value.name == "ARA_ERR_UNSUPPORTED"
+    with pytest.raises(L.AraError) as ei:
+        A.Batch(yet, [fused, f32])
+    assert ei.value.name == "ARA_ERR_INVALID_ARG"
+    with pytest.raises(L.AraError) as ei:
+        A.Batch(yet, [fused] * 65)
+    assert ei.value.name == "ARA_ERR_UNSUPPORTED"
+    b = A.Batch(yet, [fused, fused])  # the same layer twice is allowed
+    o = b.run()
+    assert np.array_equal(o[0].cpu().numpy(), o[1].cpu().numpy())
+
+
+def test_batch_over_empty_yet():
+    ids = np.zeros(0, np.int32)
+    off = np.zeros(11, np.int64)
+    _, _, spec = W.random_case(6, 1, 1.0, 100, 2, 50)
+    yet = _yet(ids, off, 10, 100)
+    lay = A.Layer(yet, spec, "fp64", "fused")
+    outs = A.Batch(yet, [lay, lay]).run([torch.full((10,), 7.0, dtype=torch.float64, device="cuda") for _ in range(2)])
+    assert all(np.array_equal(o.cpu().numpy(), np.zeros(10)) for o in outs)
