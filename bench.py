@@ -97,6 +97,71 @@ def cpu_baseline(wl, spec, target_s):
             "cpu_model": cpu_model(), "seconds": dt}
 
 
+def batch_leg(A, W, torch, n_trials, steps, precision="fp64"):
+    """64 layers over one YET of Poisson(1000)-length trials: one batched pass
+    (records built once, launch shape tuned, graph replayed) against 64
+    sequential single-layer passes over the same YET."""
+    import numpy as np
+
+    wl = W.batch_layers(n_trials)
+    log(f"batch leg: generating YET of {n_trials} Poisson(1000) trials, {len(wl.layers)} layers")
+    ids, off = W.yet_full(wl.yet)
+    t_ids = torch.from_numpy(ids).cuda()
+    t_off = torch.from_numpy(off).cuda()
+    n_events = len(ids)
+    del ids
+    yet = A.Yet(t_ids, t_off, wl.yet.n_trials, wl.yet.catalog_size)
+    t0 = time.perf_counter()
+    layers = [A.Layer(yet, s, precision, "fused") for s in wl.layers]
+    layer_build_s = time.perf_counter() - t0
+    T = wl.yet.n_trials
+    outs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in layers]
+    seq = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in layers]
+    t0 = time.perf_counter()
+    batch = A.Batch(yet, layers)
+    batch_build_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    batch.run(outs)
+    torch.cuda.synchronize()
+    first_run_ms = (time.perf_counter() - t0) * 1e3
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(n):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    batch_ms = timed(lambda: batch.run(outs), steps)
+    seq_ms = timed(lambda: [A.run_layer(yet, l, out=o) for l, o in zip(layers, seq)], max(1, steps // 2))
+    same = all(torch.equal(a, b) for a, b in zip(outs, seq))
+    J = [s.n_elts for s in wl.layers]
+    lt = len(layers) * T
+    log(f"batch leg: batched {batch_ms:.2f} ms vs sequential {seq_ms:.2f} ms ({seq_ms / batch_ms:.1f}x), "
+        f"bitwise equal {same}")
+    res = {"workload": wl.name, "n_layers": len(layers), "n_trials": T, "n_events": n_events,
+           "elts_total": int(sum(J)), "precision": precision,
+           "batched_ms": batch_ms, "sequential_ms": seq_ms, "speedup": seq_ms / batch_ms,
+           "batched_layer_trials_per_s": lt / (batch_ms * 1e-3),
+           "sequential_layer_trials_per_s": lt / (seq_ms * 1e-3),
+           "batched_lookups_per_s": float(sum(J)) * n_events / (batch_ms * 1e-3),
+           "launch_config": list(batch.launch_config), "record_bytes": batch.device_bytes,
+           "batch_build_ms": batch_build_ms, "first_run_ms_incl_tuning": first_run_ms,
+           "layer_build_s_total": layer_build_s, "bitwise_equal_to_sequential": bool(same)}
+    batch.close()
+    for l in layers:
+        l.close()
+    yet.close()
+    del t_ids, t_off, outs, seq
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,7 +173,23 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-trials", type=int, default=1_000_000)
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="only run a plain device-to-device copy of this many GiB 5 times (counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_calibration > 0:
+        import torch
+
+        n = int(args.copy_calibration * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 5}), flush=True)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -170,6 +251,15 @@ def main():
             A.pml_tvar(ylt, rps)
         extras["pml_tvar_ms"] = round((time.perf_counter() - t) * 200, 4)
 
+    lay_layout, lay_prec = lay.layout, lay.precision
+    del t_ids
+    yet.close()
+    lay.close()
+    torch.cuda.empty_cache()
+    batch = None
+    if not args.no_batch:
+        batch = batch_leg(A, W, torch, args.batch_trials, max(3, args.steps // 4))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -190,20 +280,21 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f32c-scan+f64-aggregate",
         "data": "synthetic (seeded; the paper's YET/ELT shapes, its data are not public)",
         "config": {"workload": wl.name, "n_trials": T, "events_per_trial": K, "catalog": wl.yet.catalog_size,
-                   "elts": J, "elt_size": 20_000, "layout": lay.layout, "precision": lay.precision,
+                   "elts": J, "elt_size": 20_000, "layout": lay_layout, "precision": lay_prec,
                    "return_periods": rps},
         "trial_events_per_s": T * K / (ms_step * 1e-3),
         "kernel_ms": k_ms,
         "hbm_gbps_algorithmic": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBPS, "traffic": None,
-                     "kernel": "k_trial_pass_fused" if lay.layout == "fused" else "k_trial_pass",
+                     "kernel": "k_trial_pass_fused" if lay_layout == "fused" else "k_trial_pass",
                      "algorithmic_bytes": algo_bytes},
         "cpu_baseline": cpu,
         "pml": pml.tolist(),
         "tvar": tvar.tolist(),
         "device": torch.cuda.get_device_name(0),
         "extras": extras,
+        "batch": batch,
     }
     print(json.dumps(rec), flush=True)
 
