@@ -23,6 +23,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1412_4556_amd", "csrc", "ara_kernels.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "k_trial_pass_fused_counters_plain_1M_trials_x_1000_events_16_elts.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused pass from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    import re
+
+    try:
+        text = open(COUNTERS).read()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+        if f"kernel_source_sha256_16: {sha}" not in text:
+            return None
+        return float(re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", text).group(1))
+    except (OSError, AttributeError):
+        return None
 
 
 def log(*a):
@@ -286,7 +304,9 @@ def main():
         "kernel_ms": k_ms,
         "hbm_gbps_algorithmic": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBPS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBPS,
+                     "traffic": measured_traffic() if (lay_layout == "fused" and lay_prec == "fp64" and T == 1_000_000)
+                     else None,
                      "kernel": "k_trial_pass_fused" if lay_layout == "fused" else "k_trial_pass",
                      "algorithmic_bytes": algo_bytes},
         "cpu_baseline": cpu,
