@@ -51,6 +51,7 @@ typedef int32_t ara_status;
 #define ARA_ERR_UNSUPPORTED -8  /* a valid request this build does not handle (e.g. too many ELTs) */
 
 #define ARA_MAX_ELTS 32         /* ELTs per layer; the paper's layers cover 3 to 30 */
+#define ARA_MAX_BATCH 64        /* layers per batch, YLTs per ara_pml_tvar_many call */
 
 typedef struct ara_yet_s *ara_yet;
 typedef struct ara_layer_s *ara_layer;
@@ -165,13 +166,19 @@ ara_status ara_run_layer_events(ara_yet yet, ara_layer layer, double *d_ylt, dou
  * ara_create_batch is synchronous; the batch owns its device memory.
  * ara_run_batch writes d_ylts[l] (binary64 [n_trials], caller-owned) for
  * every layer l of the batch; each is bitwise the YLT ara_run_layer gives
- * for that layer.  The launch is replayed from a HIP graph captured on the
- * first run.  Asynchronous on hip_stream. */
-#define ARA_MAX_BATCH 64
+ * for that layer.  The launch shape is chosen on the first run by timing
+ * candidates (and remembered per precision, power-of-two layer count and
+ * YET), then the pass is replayed from a HIP graph captured once.
+ * Asynchronous on hip_stream. */
 typedef struct ara_batch_s *ara_batch;
 ara_status ara_create_batch(ara_yet yet, const ara_layer *layers, int32_t n_layers, ara_batch *out);
 ara_status ara_run_batch(ara_batch batch, double *const *d_ylts, void *hip_stream);
 size_t ara_batch_device_bytes(ara_batch batch);
+/* Rebuild a batch's records for other layers (same YET and precision),
+ * reusing its device memory.  Synchronous.  Once rebuilt with another number
+ * of layers, the batch launches its pass directly instead of replaying a
+ * captured graph (a server's batches change size all the time). */
+ara_status ara_batch_rebuild(ara_batch batch, const ara_layer *layers, int32_t n_layers);
 /* Launch shape chosen for the batch (0, 0 before its first run). */
 ara_status ara_batch_launch_config(ara_batch batch, int32_t *threads, int32_t *wg_per_cu);
 void ara_destroy_batch(ara_batch batch);
@@ -191,6 +198,45 @@ ara_status ara_run_layers(ara_yet yet, const ara_layer *layers, double *const *d
  * SYNCHRONOUS: returns once the results are on the host. */
 ara_status ara_pml_tvar(const double *d_ylt, int64_t n_trials, const double *h_return_periods, int32_t n_rp,
                         double *h_pml, double *h_tvar, void *hip_stream);
+
+/* A pool of ELTs resident on the device, from which layers are built on the
+ * GPU (for ad hoc queries against a resident YET: the ELTs are loaded once,
+ * each query picks some of them and brings its own terms).
+ *   h_elt_ids / h_elt_losses / h_elt_sizes  as for ara_create_layer (COPIED).
+ *   precision   of every layer built from the pool.
+ *   max_layers  number of layers from this pool that may exist at once; the
+ *               pool allocates their fused tables up front ((catalog + 1)
+ *               values + LDS filter each, plus a binary32 scratch of catalog
+ *               entries for FP32C), which is the memory budget a server
+ *               admits queries against.
+ * Synchronous. */
+typedef struct ara_pool_s *ara_pool;
+ara_status ara_create_pool(ara_yet yet, int32_t n_elts, const int32_t *h_elt_ids, const double *h_elt_losses,
+                           const int64_t *h_elt_sizes, int32_t precision, int32_t max_layers, ara_pool *out);
+void ara_destroy_pool(ara_pool pool);  /* waits for the device; destroy the pool's layers first */
+size_t ara_pool_device_bytes(ara_pool pool);
+int32_t ara_pool_free_slots(ara_pool pool);  /* layer slots free now, -1 for NULL */
+
+/* A fused layer (ARA_LAYOUT_FUSED, the pool's precision) of pool ELTs
+ * h_elt_index[0 .. n_elts) in that order, with the given terms (as for
+ * ara_create_layer).  Built on the GPU, ASYNCHRONOUSLY on hip_stream: work on
+ * other streams through this library waits for the build.  Returns
+ * ARA_ERR_OOM, with nothing changed, when every slot of the pool is taken.
+ * ara_destroy_layer returns the slot at once, without waiting for the device:
+ * the caller destroys such a layer only when no queued work still reads it
+ * (or when that work is ordered before the slot's next build, e.g. on the
+ * same stream).  The YLT is bitwise the one of the same layer built by
+ * ara_create_layer. */
+ara_status ara_create_layer_from_pool(ara_pool pool, int32_t n_elts, const int32_t *h_elt_index, const double *h_ret,
+                                      const double *h_lim, double occ_ret, double occ_lim, double agg_ret,
+                                      double agg_lim, void *hip_stream, ara_layer *out);
+
+/* PML and TVaR of n_ylts YLTs of the same length at once (as ara_pml_tvar
+ * for each): h_pml / h_tvar are [n_ylts][n_rp] row-major.  1 <= n_ylts <=
+ * ARA_MAX_BATCH.  SYNCHRONOUS. */
+ara_status ara_pml_tvar_many(const double *const *d_ylts, int32_t n_ylts, int64_t n_trials,
+                             const double *h_return_periods, int32_t n_rp, double *h_pml, double *h_tvar,
+                             void *hip_stream);
 
 /* Device bytes a layer holds (for memory admission). */
 size_t ara_layer_device_bytes(ara_layer layer);

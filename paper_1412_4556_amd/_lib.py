@@ -42,6 +42,13 @@ SIGNATURES = {
     "ara_batch_device_bytes": (_SZ, [_P]),
     "ara_batch_launch_config": (_I32, [_P, _P, _P]),
     "ara_destroy_batch": (None, [_P]),
+    "ara_batch_rebuild": (_I32, [_P, _P, _I32]),
+    "ara_create_pool": (_I32, [_P, _I32, _P, _P, _P, _I32, _I32, _P]),
+    "ara_destroy_pool": (None, [_P]),
+    "ara_pool_device_bytes": (_SZ, [_P]),
+    "ara_pool_free_slots": (_I32, [_P]),
+    "ara_create_layer_from_pool": (_I32, [_P, _I32, _P, _P, _P, _D, _D, _D, _D, _P, _P]),
+    "ara_pml_tvar_many": (_I32, [_P, _I32, _I64, _P, _I32, _P, _P, _P]),
     "ara_pml_tvar": (_I32, [_P, _I64, _P, _I32, _P, _P, _P]),
     "ara_layer_device_bytes": (_SZ, [_P]),
     "ara_layer_layout": (_I32, [_P]),

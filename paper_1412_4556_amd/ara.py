@@ -87,6 +87,14 @@ class Layer:
         self.yet = yet
         self.spec = spec
 
+    @classmethod
+    def _wrap(cls, handle, yet, spec):
+        obj = cls.__new__(cls)
+        obj._h = handle
+        obj.yet = yet
+        obj.spec = spec
+        return obj
+
     @property
     def handle(self):
         return self._h
@@ -106,6 +114,52 @@ class Layer:
     def close(self):
         if getattr(self, "_h", None):
             L.lib().ara_destroy_layer(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pool:
+    """ELTs resident on the device; layers are built from them on the GPU."""
+
+    def __init__(self, yet: Yet, elt_ids, elt_losses, precision: str = "fp64", max_layers: int = 64):
+        sizes = _np([len(a) for a in elt_ids], np.int64)
+        ids = _np(np.concatenate(elt_ids), np.int32)
+        losses = _np(np.concatenate(elt_losses), np.float64)
+        h = ctypes.c_void_p()
+        L.check(L.lib().ara_create_pool(yet.handle, len(elt_ids), _vp(ids), _vp(losses), _vp(sizes),
+                                        PRECISIONS[precision], int(max_layers), ctypes.byref(h)))
+        self._h = h
+        self.yet = yet
+        self.n_elts = len(elt_ids)
+        self.max_layers = int(max_layers)
+
+    @property
+    def free_slots(self) -> int:
+        return int(L.lib().ara_pool_free_slots(self._h))
+
+    @property
+    def device_bytes(self) -> int:
+        return int(L.lib().ara_pool_device_bytes(self._h))
+
+    def layer(self, elt_index, ret, lim, occ_ret, occ_lim, agg_ret, agg_lim, stream=None, spec=None) -> Layer:
+        """Build a fused layer on the GPU (asynchronous on the stream); raises
+        AraError(ARA_ERR_OOM) when every slot is taken."""
+        idx = _np(elt_index, np.int32)
+        r, u = _np(ret, np.float64), _np(lim, np.float64)
+        h = ctypes.c_void_p()
+        L.check(L.lib().ara_create_layer_from_pool(self._h, len(idx), _vp(idx), _vp(r), _vp(u), float(occ_ret),
+                                                   float(occ_lim), float(agg_ret), float(agg_lim),
+                                                   ctypes.c_void_p(_stream(stream)), ctypes.byref(h)))
+        return Layer._wrap(h, self.yet, spec)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().ara_destroy_pool(self._h)
             self._h = None
 
     def __del__(self):
@@ -169,6 +223,12 @@ class Batch:
         L.check(L.lib().ara_batch_launch_config(self._h, ctypes.byref(t), ctypes.byref(w)))
         return int(t.value), int(w.value)
 
+    def rebuild(self, layers: Sequence[Layer]):
+        n = len(layers)
+        hs = (ctypes.c_void_p * n)(*[l.handle.value for l in layers])
+        L.check(L.lib().ara_batch_rebuild(self._h, hs, n))
+        self.n_layers = n
+
     def run(self, outs: Optional[Sequence[torch.Tensor]] = None, stream=None):
         if outs is None:
             outs = [torch.empty(self.yet.n_trials, dtype=torch.float64, device=self.yet.event_ids.device)
@@ -214,6 +274,21 @@ def pml_tvar(ylt: torch.Tensor, return_periods: Sequence[float], stream=None):
     tvar = np.zeros(len(rp))
     L.check(L.lib().ara_pml_tvar(ctypes.c_void_p(ylt.data_ptr()), int(ylt.numel()), _vp(rp), len(rp), _vp(pml),
                                  _vp(tvar), ctypes.c_void_p(_stream(stream))))
+    return pml, tvar
+
+
+def pml_tvar_many(ylts: Sequence[torch.Tensor], return_periods: Sequence[float], stream=None):
+    """(pml, tvar) numpy arrays [n_ylts][n_rp] for YLTs of equal length; synchronous."""
+    n = len(ylts)
+    T = ylts[0].numel()
+    for y in ylts:
+        _check_out(y, T, "ylt")
+    ps = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ylts])
+    rp = _np(list(return_periods), np.float64)
+    pml = np.zeros((n, len(rp)))
+    tvar = np.zeros((n, len(rp)))
+    L.check(L.lib().ara_pml_tvar_many(ps, n, int(T), _vp(rp), len(rp), _vp(pml), _vp(tvar),
+                                      ctypes.c_void_p(_stream(stream))))
     return pml, tvar
 
 

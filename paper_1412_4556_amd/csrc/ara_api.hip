@@ -23,9 +23,35 @@ struct ara_yet_s {
     int device = 0;
 };
 
+struct ara_pool_s;
+
 struct ara_layer_s {
     ara::LayerHost h;
     int device = 0;
+    ara_pool_s *pool = nullptr;   // layer built from a pool slot (not owned)
+    int slot = -1;
+    hipEvent_t ready = nullptr;   // recorded after the device build of a pool layer
+};
+
+// A device-resident set of ELTs from which layers are built on the GPU, and
+// a fixed number of table slots for such layers (the admission budget).
+struct ara_pool_s {
+    int32_t n_elts = 0;
+    int32_t precision = 0;
+    int32_t catalog = 0;
+    int32_t max_layers = 0;
+    int32_t fshift = 0;
+    int32_t n_fwords = 0;
+    int device = 0;
+    void *d_ids = nullptr;
+    void *d_loss = nullptr;
+    std::vector<int64_t> off;  // host [n_elts + 1]
+    std::vector<void *> occ, filt, lo;
+    std::vector<hipEvent_t> ready;
+    std::vector<int> free_slots;
+    std::mutex mu;
+    size_t slot_bytes = 0;
+    size_t bytes = 0;
 };
 
 struct ara_batch_s {
@@ -37,10 +63,14 @@ struct ara_batch_s {
     void *d_ovf_lid = nullptr;
     void *d_ovf_val = nullptr;
     double **d_ylts = nullptr;  // device array of the YLT pointers of the last run
-    double *d_agg = nullptr;    // [2n]: aggregate retentions, then limits
+    double *d_agg = nullptr;    // [2 * ARA_MAX_BATCH]: aggregate retentions, then limits
+    int32_t *d_count = nullptr; // [catalog] entries per event (record build scratch)
+    unsigned long long *d_ctr = nullptr;  // overflow total, fill cursor
+    unsigned long long ovf_cap = 0;
     std::vector<double *> h_ylts;
     ara::BatchLaunch cfg{256, 1};
     bool tuned = false;
+    bool use_graph = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     size_t bytes = 0;
@@ -116,6 +146,67 @@ void release_slot(ara::LayerHost &h, int slot, size_t bytes) {
         h.alloc[slot] = nullptr;
         h.bytes -= bytes;
     }
+}
+
+ara_status validate_elts(int32_t C, int32_t n_elts, const int32_t *h_elt_ids, const double *h_elt_losses,
+                         const int64_t *h_elt_sizes, std::vector<int64_t> &start) {
+    start.assign(n_elts + 1, 0);
+    for (int j = 0; j < n_elts; ++j) {
+        if (h_elt_sizes[j] < 0) return fail(ARA_ERR_INVALID_ARG, "negative ELT size");
+        if (h_elt_sizes[j] > C) return fail(ARA_ERR_DUP_EVENT, "ELT larger than the catalogue");
+        start[j + 1] = start[j] + h_elt_sizes[j];
+    }
+    if (start[n_elts] > 0 && (!h_elt_ids || !h_elt_losses)) return fail(ARA_ERR_INVALID_ARG, "NULL ELT arrays");
+    std::vector<int32_t> stamp;
+    try {
+        stamp.assign((size_t)C, 0);
+    } catch (const std::bad_alloc &) {
+        return fail(ARA_ERR_OOM, "host allocation");
+    }
+    for (int j = 0; j < n_elts; ++j)
+        for (int64_t n = start[j]; n < start[j + 1]; ++n) {
+            const int32_t e = h_elt_ids[n];
+            if (e < 0 || e >= C) return fail(ARA_ERR_EVENT_RANGE, "ELT event ID outside [0, catalog_size)");
+            if (stamp[e] == j + 1) return fail(ARA_ERR_DUP_EVENT, "duplicate event ID in one ELT");
+            stamp[e] = j + 1;
+            if (!finite_nonneg(h_elt_losses[n])) return fail(ARA_ERR_VALUE, "ELT loss must be finite and >= 0");
+        }
+    return ARA_OK;
+}
+
+ara_status validate_terms(int32_t n_elts, const double *h_ret, const double *h_lim, double occ_ret, double occ_lim,
+                          double agg_ret, double agg_lim) {
+    for (int j = 0; j < n_elts; ++j) {
+        if (!finite_nonneg(h_ret[j])) return fail(ARA_ERR_VALUE, "ELT retention must be finite and >= 0");
+        if (!limit_ok(h_lim[j])) return fail(ARA_ERR_VALUE, "ELT limit must be >= 0");
+    }
+    if (!finite_nonneg(occ_ret) || !limit_ok(occ_lim)) return fail(ARA_ERR_VALUE, "bad occurrence terms");
+    if (!finite_nonneg(agg_ret) || !limit_ok(agg_lim)) return fail(ARA_ERR_VALUE, "bad aggregate terms");
+    return ARA_OK;
+}
+
+void set_terms(ara::LayerHost &h, int32_t n_elts, const double *h_ret, const double *h_lim, double occ_ret,
+               double occ_lim, double agg_ret, double agg_lim) {
+    for (int j = 0; j < n_elts; ++j) {
+        h.t64.ret[j] = h_ret[j];
+        h.t64.lim[j] = h_lim[j];
+        h.t32.ret[j] = (float)h_ret[j];
+        h.t32.lim[j] = (float)h_lim[j];
+    }
+    h.t64.occ_ret = occ_ret;
+    h.t64.occ_lim = occ_lim;
+    h.t32.occ_ret = (float)occ_ret;
+    h.t32.occ_lim = (float)occ_lim;
+    h.t64.agg_ret = h.t32.agg_ret = agg_ret;
+    h.t64.agg_lim = h.t32.agg_lim = agg_lim;
+    h.t64.n_elts = h.t32.n_elts = n_elts;
+}
+
+void filter_geometry(int32_t C, int32_t &fshift, int32_t &n_fwords) {
+    fshift = 0;
+    while ((((int64_t)C + (1LL << fshift) - 1) >> fshift) > ara::kFilterBits) ++fshift;
+    const int64_t n_blocks = ((int64_t)C + (1LL << fshift) - 1) >> fshift;
+    n_fwords = (int32_t)((n_blocks + 31) / 32);
 }
 
 template <typename T>
@@ -201,10 +292,8 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
             present.reserve(rank);
             for (int64_t w = 0; w < n_words; ++w)
                 for (uint32_t x = bm[w].x; x; x &= x - 1u) present.push_back((int32_t)(w * 32 + __builtin_ctz(x)));
-            int32_t fshift = 0;
-            while ((((int64_t)C + (1LL << fshift) - 1) >> fshift) > ara::kFilterBits) ++fshift;
-            const int64_t n_blocks = ((int64_t)C + (1LL << fshift) - 1) >> fshift;
-            const int64_t n_fwords = (n_blocks + 31) / 32;
+            int32_t fshift = 0, n_fwords = 0;
+            filter_geometry((int32_t)C, fshift, n_fwords);
             const void *d_rows, *d_present;
             if ((st = upload(h, 0, rows.data(), rows.size(), &d_rows)) != ARA_OK) return st;
             if ((st = upload(h, 1, present.data(), present.size(), &d_present)) != ARA_OK) return st;
@@ -311,35 +400,11 @@ ara_status ara_create_layer(ara_yet yet, int32_t n_elts, const int32_t *h_elt_id
     if (layout < ARA_LAYOUT_AUTO || layout > ARA_LAYOUT_FUSED) return fail(ARA_ERR_INVALID_ARG, "unknown layout");
     if (!h_elt_sizes || !h_ret || !h_lim) return fail(ARA_ERR_INVALID_ARG, "NULL term or size array");
     const int32_t C = yet->catalog;
-    std::vector<int64_t> start(n_elts + 1, 0);
-    for (int j = 0; j < n_elts; ++j) {
-        if (h_elt_sizes[j] < 0) return fail(ARA_ERR_INVALID_ARG, "negative ELT size");
-        if (h_elt_sizes[j] > C) return fail(ARA_ERR_DUP_EVENT, "ELT larger than the catalogue");
-        start[j + 1] = start[j] + h_elt_sizes[j];
-    }
-    if (start[n_elts] > 0 && (!h_elt_ids || !h_elt_losses)) return fail(ARA_ERR_INVALID_ARG, "NULL ELT arrays");
-    for (int j = 0; j < n_elts; ++j) {
-        if (!finite_nonneg(h_ret[j])) return fail(ARA_ERR_VALUE, "ELT retention must be finite and >= 0");
-        if (!limit_ok(h_lim[j])) return fail(ARA_ERR_VALUE, "ELT limit must be >= 0");
-    }
-    if (!finite_nonneg(occ_ret) || !limit_ok(occ_lim)) return fail(ARA_ERR_VALUE, "bad occurrence terms");
-    if (!finite_nonneg(agg_ret) || !limit_ok(agg_lim)) return fail(ARA_ERR_VALUE, "bad aggregate terms");
-    {
-        std::vector<int32_t> stamp;
-        try {
-            stamp.assign((size_t)C, 0);
-        } catch (const std::bad_alloc &) {
-            return fail(ARA_ERR_OOM, "host allocation");
-        }
-        for (int j = 0; j < n_elts; ++j)
-            for (int64_t n = start[j]; n < start[j + 1]; ++n) {
-                int32_t e = h_elt_ids[n];
-                if (e < 0 || e >= C) return fail(ARA_ERR_EVENT_RANGE, "ELT event ID outside [0, catalog_size)");
-                if (stamp[e] == j + 1) return fail(ARA_ERR_DUP_EVENT, "duplicate event ID in one ELT");
-                stamp[e] = j + 1;
-                if (!finite_nonneg(h_elt_losses[n])) return fail(ARA_ERR_VALUE, "ELT loss must be finite and >= 0");
-            }
-    }
+    std::vector<int64_t> start;
+    ara_status vst = validate_elts(C, n_elts, h_elt_ids, h_elt_losses, h_elt_sizes, start);
+    if (vst != ARA_OK) return vst;
+    vst = validate_terms(n_elts, h_ret, h_lim, occ_ret, occ_lim, agg_ret, agg_lim);
+    if (vst != ARA_OK) return vst;
 
     ara_layer_s *L = new (std::nothrow) ara_layer_s;
     if (!L) return fail(ARA_ERR_OOM, "host allocation");
@@ -349,19 +414,7 @@ ara_status ara_create_layer(ara_yet yet, int32_t n_elts, const int32_t *h_elt_id
     h.precision = precision;
     h.layout = layout == ARA_LAYOUT_AUTO ? ARA_LAYOUT_FUSED : layout;
     h.tab.catalog = C;
-    for (int j = 0; j < n_elts; ++j) {
-        h.t64.ret[j] = h_ret[j];
-        h.t64.lim[j] = h_lim[j];
-        h.t32.ret[j] = (float)h_ret[j];
-        h.t32.lim[j] = (float)h_lim[j];
-    }
-    h.t64.occ_ret = occ_ret;
-    h.t64.occ_lim = occ_lim;
-    h.t32.occ_ret = (float)occ_ret;
-    h.t32.occ_lim = (float)occ_lim;
-    h.t64.agg_ret = h.t32.agg_ret = agg_ret;
-    h.t64.agg_lim = h.t32.agg_lim = agg_lim;
-    h.t64.n_elts = h.t32.n_elts = n_elts;
+    set_terms(h, n_elts, h_ret, h_lim, occ_ret, occ_lim, agg_ret, agg_lim);
     (void)hipGetDevice(&L->device);
 
     ara_status st = precision == ARA_FP32C ? build_tables<float>(h, h_elt_ids, h_elt_losses, start, h_elt_sizes)
@@ -377,6 +430,14 @@ ara_status ara_create_layer(ara_yet yet, int32_t n_elts, const int32_t *h_elt_id
 
 void ara_destroy_layer(ara_layer layer) {
     if (!layer) return;
+    if (layer->pool) {
+        // the slot returns to its pool without a device-wide wait; its next
+        // build is ordered after this layer's build and the caller's use of it
+        std::lock_guard<std::mutex> g(layer->pool->mu);
+        layer->pool->free_slots.push_back(layer->slot);
+        delete layer;
+        return;
+    }
     (void)hipDeviceSynchronize();
     free_layer_memory(layer->h);
     delete layer;
@@ -391,6 +452,10 @@ ara_status ara_run_layer(ara_yet yet, ara_layer layer, double *d_ylt, void *hip_
     if (!yet || !layer) return fail(ARA_ERR_INVALID_ARG, "NULL handle");
     if (layer->h.catalog != yet->catalog) return fail(ARA_ERR_INVALID_ARG, "layer built for another catalogue");
     if (yet->v.n_trials > 0 && !d_ylt) return fail(ARA_ERR_INVALID_ARG, "d_ylt is NULL");
+    if (layer->ready) {
+        hipError_t we = hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), layer->ready, 0);
+        if (we != hipSuccess) return hip_fail(we, "waiting for the layer build");
+    }
     hipError_t e = ara::launch_trial_pass(yet->v, layer->h, d_ylt, static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "trial pass launch");
     return ARA_OK;
@@ -401,84 +466,293 @@ ara_status ara_run_layer_events(ara_yet yet, ara_layer layer, double *d_ylt, dou
     if (!yet || !layer) return fail(ARA_ERR_INVALID_ARG, "NULL handle");
     if (layer->h.catalog != yet->catalog) return fail(ARA_ERR_INVALID_ARG, "layer built for another catalogue");
     if (yet->v.n_trials > 0 && !d_ylt) return fail(ARA_ERR_INVALID_ARG, "d_ylt is NULL");
+    if (layer->ready) {
+        hipError_t we = hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), layer->ready, 0);
+        if (we != hipSuccess) return hip_fail(we, "waiting for the layer build");
+    }
     hipError_t e = ara::launch_trial_pass_events(yet->v, layer->h, d_ylt, d_event_cum, d_event_net,
                                                  static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "per-event trial pass launch");
     return ARA_OK;
 }
 
+static void free_pool(ara_pool p) {
+    for (void *q : p->occ)
+        if (q) (void)hipFree(q);
+    for (void *q : p->filt)
+        if (q) (void)hipFree(q);
+    for (void *q : p->lo)
+        if (q) (void)hipFree(q);
+    for (hipEvent_t ev : p->ready)
+        if (ev) (void)hipEventDestroy(ev);
+    if (p->d_ids) (void)hipFree(p->d_ids);
+    if (p->d_loss) (void)hipFree(p->d_loss);
+    delete p;
+}
+
+static ara_status upload_pool_losses(ara_pool p, const double *h_losses, size_t n, bool fp32) {
+    const size_t vb = fp32 ? sizeof(float) : sizeof(double);
+    std::vector<float> f;
+    if (fp32) {
+        f.resize(n);
+        for (size_t i = 0; i < n; ++i) f[i] = (float)h_losses[i];
+    }
+    const void *src = fp32 ? static_cast<const void *>(f.data()) : static_cast<const void *>(h_losses);
+    hipError_t e = dev_alloc(&p->d_loss, n * vb);
+    hipStream_t s = ara::internal_stream();
+    if (e == hipSuccess && n) e = hipMemcpyAsync(p->d_loss, src, n * vb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "pool upload");
+    p->bytes += n * vb;
+    return ARA_OK;
+}
+
+ara_status ara_create_pool(ara_yet yet, int32_t n_elts, const int32_t *h_elt_ids, const double *h_elt_losses,
+                           const int64_t *h_elt_sizes, int32_t precision, int32_t max_layers, ara_pool *out) {
+    if (!out) return fail(ARA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!yet || !h_elt_sizes) return fail(ARA_ERR_INVALID_ARG, "NULL yet or sizes");
+    if (n_elts < 1) return fail(ARA_ERR_INVALID_ARG, "n_elts < 1");
+    if (max_layers < 1) return fail(ARA_ERR_INVALID_ARG, "max_layers < 1");
+    if (precision != ARA_FP64 && precision != ARA_FP32C) return fail(ARA_ERR_INVALID_ARG, "unknown precision");
+    std::vector<int64_t> start;
+    ara_status st = validate_elts(yet->catalog, n_elts, h_elt_ids, h_elt_losses, h_elt_sizes, start);
+    if (st != ARA_OK) return st;
+    ara_pool_s *p = new (std::nothrow) ara_pool_s;
+    if (!p) return fail(ARA_ERR_OOM, "host allocation");
+    p->n_elts = n_elts;
+    p->precision = precision;
+    p->catalog = yet->catalog;
+    p->max_layers = max_layers;
+    p->off = start;
+    (void)hipGetDevice(&p->device);
+    filter_geometry(yet->catalog, p->fshift, p->n_fwords);
+    const size_t total = (size_t)start[n_elts];
+    hipStream_t s = ara::internal_stream();
+    hipError_t e = dev_alloc(&p->d_ids, total * sizeof(int32_t));
+    if (e == hipSuccess && total)
+        e = hipMemcpyAsync(p->d_ids, h_elt_ids, total * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_pool(p);
+        return hip_fail(e, "pool upload");
+    }
+    p->bytes += total * sizeof(int32_t);
+    st = upload_pool_losses(p, h_elt_losses, total, precision == ARA_FP32C);
+    if (st != ARA_OK) {
+        free_pool(p);
+        return st;
+    }
+    const size_t C = (size_t)yet->catalog;
+    const size_t occ_bytes = (C + 1) * (precision == ARA_FP32C ? sizeof(float) : sizeof(double));
+    const size_t filt_bytes = (size_t)p->n_fwords * sizeof(uint32_t);
+    const size_t lo_bytes = precision == ARA_FP32C ? C * sizeof(float) : 0;
+    p->slot_bytes = occ_bytes + filt_bytes + lo_bytes;
+    p->occ.assign(max_layers, nullptr);
+    p->filt.assign(max_layers, nullptr);
+    p->lo.assign(max_layers, nullptr);
+    p->ready.assign(max_layers, nullptr);
+    for (int i = 0; i < max_layers && e == hipSuccess; ++i) {
+        e = dev_alloc(&p->occ[i], occ_bytes);
+        if (e == hipSuccess) e = dev_alloc(&p->filt[i], filt_bytes);
+        if (e == hipSuccess && lo_bytes) e = dev_alloc(&p->lo[i], lo_bytes);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ready[i], hipEventDisableTiming);
+        p->free_slots.push_back(max_layers - 1 - i);
+    }
+    if (e != hipSuccess) {
+        free_pool(p);
+        return hip_fail(e, "pool layer slots");
+    }
+    p->bytes += p->slot_bytes * (size_t)max_layers;
+    *out = p;
+    return ARA_OK;
+}
+
+void ara_destroy_pool(ara_pool pool) {
+    if (!pool) return;
+    (void)hipDeviceSynchronize();
+    free_pool(pool);
+}
+
+size_t ara_pool_device_bytes(ara_pool pool) { return pool ? pool->bytes : 0; }
+
+int32_t ara_pool_free_slots(ara_pool pool) {
+    if (!pool) return -1;
+    std::lock_guard<std::mutex> g(pool->mu);
+    return (int32_t)pool->free_slots.size();
+}
+
+ara_status ara_create_layer_from_pool(ara_pool pool, int32_t n_elts, const int32_t *h_elt_index, const double *h_ret,
+                                      const double *h_lim, double occ_ret, double occ_lim, double agg_ret,
+                                      double agg_lim, void *hip_stream, ara_layer *out) {
+    if (!out) return fail(ARA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!pool || !h_elt_index || !h_ret || !h_lim) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    if (n_elts < 1) return fail(ARA_ERR_INVALID_ARG, "n_elts < 1");
+    if (n_elts > ARA_MAX_ELTS) return fail(ARA_ERR_UNSUPPORTED, "n_elts exceeds ARA_MAX_ELTS");
+    for (int j = 0; j < n_elts; ++j)
+        if (h_elt_index[j] < 0 || h_elt_index[j] >= pool->n_elts) return fail(ARA_ERR_INVALID_ARG, "ELT index outside the pool");
+    ara_status st = validate_terms(n_elts, h_ret, h_lim, occ_ret, occ_lim, agg_ret, agg_lim);
+    if (st != ARA_OK) return st;
+    int slot = -1;
+    {
+        std::lock_guard<std::mutex> g(pool->mu);
+        if (pool->free_slots.empty()) return fail(ARA_ERR_OOM, "no free layer slot in the pool");
+        slot = pool->free_slots.back();
+        pool->free_slots.pop_back();
+    }
+    ara_layer_s *L = new (std::nothrow) ara_layer_s;
+    if (!L) {
+        std::lock_guard<std::mutex> g(pool->mu);
+        pool->free_slots.push_back(slot);
+        return fail(ARA_ERR_OOM, "host allocation");
+    }
+    L->pool = pool;
+    L->slot = slot;
+    L->ready = pool->ready[slot];
+    L->device = pool->device;
+    ara::LayerHost &h = L->h;
+    h.n_elts = n_elts;
+    h.catalog = pool->catalog;
+    h.precision = pool->precision;
+    h.layout = ara::kFused;
+    h.tab.catalog = pool->catalog;
+    h.tab.occ = pool->occ[slot];
+    h.tab.filt = static_cast<const uint32_t *>(pool->filt[slot]);
+    h.tab.fshift = pool->fshift;
+    h.tab.n_fwords = pool->n_fwords;
+    h.bytes = pool->slot_bytes;
+    set_terms(h, n_elts, h_ret, h_lim, occ_ret, occ_lim, agg_ret, agg_lim);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = ara::launch_pool_layer(h, static_cast<const int32_t *>(pool->d_ids), pool->d_loss, pool->off.data(),
+                                          h_elt_index, n_elts, static_cast<float *>(pool->lo[slot]), s);
+    if (e == hipSuccess) e = hipEventRecord(L->ready, s);
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> g(pool->mu);
+        pool->free_slots.push_back(slot);
+        delete L;
+        return hip_fail(e, "building the layer from the pool");
+    }
+    *out = L;
+    return ARA_OK;
+}
+
 static void free_batch(ara_batch b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (void *p : {b->d_rec, b->d_ovf_lid, b->d_ovf_val, (void *)b->d_ylts, (void *)b->d_agg})
+    for (void *p : {b->d_rec, b->d_ovf_lid, b->d_ovf_val, (void *)b->d_ylts, (void *)b->d_agg, (void *)b->d_count,
+                     (void *)b->d_ctr})
         if (p) (void)hipFree(p);
     delete b;
+}
+
+static ara_status check_batch_layers(int32_t catalog, const ara_layer *layers, int32_t n_layers, int32_t *prec,
+                                     const void **occ) {
+    if (!layers) return fail(ARA_ERR_INVALID_ARG, "NULL layers");
+    if (n_layers < 1) return fail(ARA_ERR_INVALID_ARG, "n_layers < 1");
+    if (n_layers > ARA_MAX_BATCH) return fail(ARA_ERR_UNSUPPORTED, "n_layers exceeds ARA_MAX_BATCH");
+    for (int l = 0; l < n_layers; ++l) {
+        if (!layers[l]) return fail(ARA_ERR_INVALID_ARG, "NULL layer handle");
+        const ara::LayerHost &h = layers[l]->h;
+        if (h.catalog != catalog) return fail(ARA_ERR_INVALID_ARG, "layer built for another catalogue");
+        if (h.layout != ara::kFused) return fail(ARA_ERR_UNSUPPORTED, "batched layers must use the fused layout");
+        if (*prec >= 0 && h.precision != *prec) return fail(ARA_ERR_INVALID_ARG, "layers of different precisions");
+        *prec = h.precision;
+        occ[l] = h.tab.occ;
+    }
+    return ARA_OK;
+}
+
+ara_status ara_batch_rebuild(ara_batch b, const ara_layer *layers, int32_t n_layers) {
+    if (!b) return fail(ARA_ERR_INVALID_ARG, "NULL batch");
+    const void *occ[ARA_MAX_BATCH];
+    int32_t prec = b->precision;
+    ara_status st = check_batch_layers(b->catalog, layers, n_layers, &prec, occ);
+    if (st != ARA_OK) return st;
+    const bool fp64 = prec == ARA_FP64;
+    const size_t val_bytes = fp64 ? 8 : 4;
+    hipStream_t s = ara::internal_stream();
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < n_layers && e == hipSuccess; ++l)
+        if (layers[l]->ready) e = hipStreamWaitEvent(s, layers[l]->ready, 0);
+    unsigned long long h_ctr[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_ctr, h_ctr, sizeof(h_ctr), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = ara::launch_batch_count(occ, n_layers, b->catalog, fp64, b->d_count, b->d_ctr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_ctr, b->d_ctr, sizeof(h_ctr), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "counting the batch records");
+    const unsigned long long n_ovf = h_ctr[0];
+    if (n_ovf >= (1ULL << 32)) return fail(ARA_ERR_UNSUPPORTED, "too many overflow entries for one batch");
+    if (n_ovf > b->ovf_cap) {
+        // grows only; freeing waits for the device
+        if (b->d_ovf_lid) (void)hipFree(b->d_ovf_lid);
+        if (b->d_ovf_val) (void)hipFree(b->d_ovf_val);
+        b->d_ovf_lid = b->d_ovf_val = nullptr;
+        b->bytes -= (size_t)b->ovf_cap * (1 + val_bytes);
+        b->ovf_cap = 0;
+        e = dev_alloc(&b->d_ovf_lid, (size_t)n_ovf);
+        if (e == hipSuccess) e = dev_alloc(&b->d_ovf_val, (size_t)n_ovf * val_bytes);
+        if (e != hipSuccess) return hip_fail(e, "batch overflow area");
+        b->ovf_cap = n_ovf;
+        b->bytes += (size_t)n_ovf * (1 + val_bytes);
+    }
+    std::vector<double> agg(2 * ARA_MAX_BATCH, 0.0);
+    for (int l = 0; l < n_layers; ++l) {
+        agg[l] = layers[l]->h.t64.agg_ret;
+        agg[ARA_MAX_BATCH + l] = layers[l]->h.t64.agg_lim;
+    }
+    e = hipMemcpyAsync(b->d_agg, agg.data(), sizeof(double) * agg.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = ara::launch_batch_fill(occ, n_layers, b->catalog, fp64, b->d_count, b->d_rec,
+                                   static_cast<uint8_t *>(b->d_ovf_lid), b->d_ovf_val, b->d_ctr + 1, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "building the batch records");
+    if (n_layers != b->n) {
+        // a batch whose size changes (a server's) launches directly from now
+        // on instead of capturing a graph per size
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        b->tuned = false;
+        b->use_graph = b->n == 0;
+        b->n = n_layers;
+    }
+    b->h_ylts.assign(n_layers, nullptr);
+    return ARA_OK;
 }
 
 ara_status ara_create_batch(ara_yet yet, const ara_layer *layers, int32_t n_layers, ara_batch *out) {
     if (!out) return fail(ARA_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (!yet || !layers) return fail(ARA_ERR_INVALID_ARG, "NULL yet or layers");
-    if (n_layers < 1) return fail(ARA_ERR_INVALID_ARG, "n_layers < 1");
-    if (n_layers > ARA_MAX_BATCH) return fail(ARA_ERR_UNSUPPORTED, "n_layers exceeds ARA_MAX_BATCH");
+    if (!yet) return fail(ARA_ERR_INVALID_ARG, "NULL yet");
     const void *occ[ARA_MAX_BATCH];
     int32_t prec = -1;
-    for (int l = 0; l < n_layers; ++l) {
-        if (!layers[l]) return fail(ARA_ERR_INVALID_ARG, "NULL layer handle");
-        const ara::LayerHost &h = layers[l]->h;
-        if (h.catalog != yet->catalog) return fail(ARA_ERR_INVALID_ARG, "layer built for another catalogue");
-        if (h.layout != ara::kFused) return fail(ARA_ERR_UNSUPPORTED, "batched layers must use the fused layout");
-        if (prec >= 0 && h.precision != prec) return fail(ARA_ERR_INVALID_ARG, "layers of different precisions");
-        prec = h.precision;
-        occ[l] = h.tab.occ;
-    }
+    ara_status st = check_batch_layers(yet->catalog, layers, n_layers, &prec, occ);
+    if (st != ARA_OK) return st;
     ara_batch_s *b = new (std::nothrow) ara_batch_s;
     if (!b) return fail(ARA_ERR_OOM, "host allocation");
     b->yv = yet->v;
-    b->n = n_layers;
     b->precision = prec;
     b->catalog = yet->catalog;
     (void)hipGetDevice(&b->device);
-    const bool fp64 = prec == ARA_FP64;
-    const size_t rec_bytes = fp64 ? 64 : 32, val_bytes = fp64 ? 8 : 4;
     const size_t C = (size_t)yet->catalog;
-    hipStream_t s = ara::internal_stream();
-    int32_t *d_count = nullptr;
-    unsigned long long *d_ctr = nullptr;  // [0] overflow total, [1] fill cursor
-    unsigned long long h_ctr[2] = {0, 0};
-    hipError_t e = dev_alloc(reinterpret_cast<void **>(&d_count), C * sizeof(int32_t));
-    if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&d_ctr), sizeof(h_ctr));
-    if (e == hipSuccess) e = hipMemcpyAsync(d_ctr, h_ctr, sizeof(h_ctr), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = ara::launch_batch_count(occ, n_layers, yet->catalog, fp64, d_count, d_ctr, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(h_ctr, d_ctr, sizeof(h_ctr), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    const unsigned long long n_ovf = h_ctr[0];
-    if (e == hipSuccess && n_ovf >= (1ULL << 32)) e = hipErrorInvalidValue;
-    if (e == hipSuccess) e = dev_alloc(&b->d_rec, C * rec_bytes);
-    if (e == hipSuccess) e = dev_alloc(&b->d_ovf_lid, (size_t)n_ovf);
-    if (e == hipSuccess) e = dev_alloc(&b->d_ovf_val, (size_t)n_ovf * val_bytes);
-    if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_ylts), sizeof(double *) * n_layers);
-    if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_agg), sizeof(double) * 2 * n_layers);
-    std::vector<double> agg(2 * n_layers);
-    for (int l = 0; l < n_layers; ++l) {
-        agg[l] = layers[l]->h.t64.agg_ret;
-        agg[n_layers + l] = layers[l]->h.t64.agg_lim;
-    }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_agg, agg.data(), sizeof(double) * agg.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = ara::launch_batch_fill(occ, n_layers, yet->catalog, fp64, d_count, b->d_rec,
-                                   static_cast<uint8_t *>(b->d_ovf_lid), b->d_ovf_val, d_ctr + 1, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (d_count) (void)hipFree(d_count);
-    if (d_ctr) (void)hipFree(d_ctr);
+    const size_t rec_bytes = prec == ARA_FP64 ? 64 : 32;
+    hipError_t e = dev_alloc(&b->d_rec, C * rec_bytes);
+    if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_count), C * sizeof(int32_t));
+    if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_ctr), 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_ylts), sizeof(double *) * ARA_MAX_BATCH);
+    if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_agg), sizeof(double) * 2 * ARA_MAX_BATCH);
     if (e != hipSuccess) {
         free_batch(b);
-        return hip_fail(e, "building the batch records");
+        return hip_fail(e, "batch allocation");
     }
-    b->bytes = C * rec_bytes + (size_t)n_ovf * (1 + val_bytes) + sizeof(double *) * n_layers +
-               sizeof(double) * 2 * n_layers;
-    b->h_ylts.assign(n_layers, nullptr);
+    b->bytes = C * (rec_bytes + sizeof(int32_t)) + 16 + (sizeof(double *) + 2 * sizeof(double)) * ARA_MAX_BATCH;
+    st = ara_batch_rebuild(b, layers, n_layers);
+    if (st != ARA_OK) {
+        free_batch(b);
+        return st;
+    }
     *out = b;
     return ARA_OK;
 }
@@ -500,7 +774,7 @@ ara::BatchTables batch_tables(ara_batch b) {
     t.ovf_val = b->d_ovf_val;
     t.ylts = b->d_ylts;
     t.agg_ret = b->d_agg;
-    t.agg_lim = b->d_agg + b->n;
+    t.agg_lim = b->d_agg + ARA_MAX_BATCH;
     t.n_layers = b->n;
     return t;
 }
@@ -513,7 +787,9 @@ std::map<std::tuple<int, int, int64_t, int, int>, ara::BatchLaunch> g_tuned;
 hipError_t tune_batch(ara_batch b, hipStream_t s) {
     const bool fp64 = b->precision == ARA_FP64;
     const int form = b->yv.offsets ? 1 : 0;
-    const auto key = std::make_tuple(b->precision, b->n, b->yv.n_trials, form, (int)b->yv.aligned16);
+    int n_bucket = 1;  // layer counts share a tuned shape per power of two
+    while (n_bucket < b->n) n_bucket <<= 1;
+    const auto key = std::make_tuple(b->precision, n_bucket, b->yv.n_trials, form, (int)b->yv.aligned16);
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tuned.find(key);
@@ -530,8 +806,8 @@ hipError_t tune_batch(ara_batch b, hipStream_t s) {
         if (std::sscanf(force, "%d,%d", &t, &w) == 2 && t >= 64 && t <= 512 && t % 64 == 0 && w >= 1) cands.push_back({t, w});
     }
     if (cands.empty())
-        for (int t : {128, 256, 512})
-            for (int w : {1, 2, 4, 8})
+        for (int t : {256, 512})
+            for (int w : {1, 2, 4})
                 if (ara::batch_lds_bytes(b->n, t) * (size_t)w <= 160u * 1024u) cands.push_back({t, w});
     if (cands.empty()) cands.push_back({64, 1});
     const ara::BatchTables tb = batch_tables(b);
@@ -613,6 +889,11 @@ ara_status ara_run_batch(ara_batch batch, double *const *d_ylts, void *hip_strea
         e = tune_batch(batch, s);
         if (e != hipSuccess) return hip_fail(e, "batch launch tuning");
     }
+    if (!batch->use_graph) {
+        e = ara::launch_batch_pass(batch->yv, batch_tables(batch), batch->precision == ARA_FP64, batch->cfg, s);
+        if (e != hipSuccess) return hip_fail(e, "batch launch");
+        return ARA_OK;
+    }
     if (!batch->exec) {
         e = capture_batch(batch);
         if (e != hipSuccess) return hip_fail(e, "batch graph capture");
@@ -642,25 +923,46 @@ ara_status ara_run_layers(ara_yet yet, const ara_layer *layers, double *const *d
     return ARA_OK;
 }
 
-ara_status ara_pml_tvar(const double *d_ylt, int64_t n_trials, const double *h_return_periods, int32_t n_rp,
-                        double *h_pml, double *h_tvar, void *hip_stream) {
-    if (!d_ylt || !h_return_periods || !h_pml || !h_tvar) return fail(ARA_ERR_INVALID_ARG, "NULL pointer");
+static ara_status tail_sizes(int64_t n_trials, const double *h_return_periods, int32_t n_rp, int64_t *k) {
     if (n_trials < 1 || n_trials > 2147483647LL) return fail(ARA_ERR_INVALID_ARG, "n_trials outside 1 .. 2^31-1");
     if (n_rp < 1 || n_rp > 16) return fail(ARA_ERR_INVALID_ARG, "n_rp outside 1 .. 16");
-    int64_t k[16];
     for (int r = 0; r < n_rp; ++r) {
-        double N = h_return_periods[r];
+        const double N = h_return_periods[r];
         if (!(N > 0.0) || !std::isfinite(N)) return fail(ARA_ERR_INVALID_ARG, "return period must be finite and > 0");
-        double kk = std::floor((double)n_trials / N);
+        const double kk = std::floor((double)n_trials / N);
         if (kk < 1.0) return fail(ARA_ERR_RP, "return period leaves no tail trial (floor(T/N) < 1)");
         if (kk > (double)n_trials) return fail(ARA_ERR_RP, "return period shorter than one year (floor(T/N) > T)");
         k[r] = (int64_t)kk;
     }
+    return ARA_OK;
+}
+
+ara_status ara_pml_tvar(const double *d_ylt, int64_t n_trials, const double *h_return_periods, int32_t n_rp,
+                        double *h_pml, double *h_tvar, void *hip_stream) {
+    if (!d_ylt || !h_return_periods || !h_pml || !h_tvar) return fail(ARA_ERR_INVALID_ARG, "NULL pointer");
+    return ara_pml_tvar_many(&d_ylt, 1, n_trials, h_return_periods, n_rp, h_pml, h_tvar, hip_stream);
+}
+
+ara_status ara_pml_tvar_many(const double *const *d_ylts, int32_t n_ylts, int64_t n_trials,
+                             const double *h_return_periods, int32_t n_rp, double *h_pml, double *h_tvar,
+                             void *hip_stream) {
+    if (!d_ylts || !h_return_periods || !h_pml || !h_tvar) return fail(ARA_ERR_INVALID_ARG, "NULL pointer");
+    if (n_ylts < 1 || n_ylts > ARA_MAX_BATCH) return fail(ARA_ERR_INVALID_ARG, "n_ylts outside 1 .. ARA_MAX_BATCH");
+    for (int i = 0; i < n_ylts; ++i)
+        if (!d_ylts[i]) return fail(ARA_ERR_INVALID_ARG, "NULL YLT pointer");
+    int64_t k[16];
+    ara_status st = tail_sizes(n_trials, h_return_periods, n_rp, k);
+    if (st != ARA_OK) return st;
+    std::vector<double> out(2 * (size_t)n_ylts * n_rp);
     int32_t nan = 0;
-    hipError_t e = ara::pml_tvar_device(d_ylt, n_trials, k, n_rp, h_pml, h_tvar, &nan,
+    hipError_t e = ara::pml_tvar_device(d_ylts, n_ylts, n_trials, k, n_rp, out.data(), &nan,
                                         static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "PML/TVaR");
-    if (nan) return fail(ARA_ERR_VALUE, "the YLT holds NaN");
+    if (nan) return fail(ARA_ERR_VALUE, "a YLT holds NaN");
+    for (int i = 0; i < n_ylts * n_rp; ++i) {
+        h_pml[i] = out[2 * i];
+        h_tvar[i] = out[2 * i + 1];
+    }
     return ARA_OK;
 }
 

@@ -135,11 +135,16 @@ hipError_t launch_batch_fill(const void *const *occ, int32_t n_layers, int32_t c
                              unsigned long long *d_ovf_cursor, hipStream_t s);
 hipError_t launch_batch_pass(const YetView &y, const BatchTables &b, bool fp64, const BatchLaunch &cfg, hipStream_t s);
 size_t batch_lds_bytes(int32_t n_layers, int threads);
+// Fused table of a layer from pool ELTs idx[0..n) (host offsets off[]),
+// enqueued on s; d_lo: binary32 scratch [catalog] for FP32C, else unused.
+hipError_t launch_pool_layer(LayerHost &L, const int32_t *d_ids, const void *d_loss, const int64_t *h_off,
+                             const int32_t *h_idx, int32_t n, float *d_lo, hipStream_t s);
 // d[0 .. n) = 0 with a kernel (no memset node if the caller captures a graph)
 hipError_t launch_fill_zero(double *d, int64_t n, hipStream_t s);
 
-// Selection (ara_select.hip): PML / TVaR for n_rp tail sizes k[r].
-hipError_t pml_tvar_device(const double *d_ylt, int64_t n, const int64_t *h_k, int32_t n_rp, double *h_pml,
-                           double *h_tvar, int32_t *h_nan, hipStream_t s);
+// Selection (ara_select.hip): PML / TVaR of n_ylt YLTs of length n for n_rp
+// tail sizes k[r]; h_out[2 * (y * n_rp + r)] = PML, [... + 1] = TVaR.
+hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n, const int64_t *h_k, int32_t n_rp,
+                           double *h_out, int32_t *h_nan, hipStream_t s);
 
 }  // namespace ara

@@ -654,6 +654,46 @@ __global__ __launch_bounds__(512) void k_trial_pass_batch(YetView y, const int64
     }
 }
 
+// --------------------------------------------------------------------------------------------
+// layers built on the device from a resident ELT pool: the fused table is
+// accumulated ELT by ELT in layer order (one kernel per ELT, an ELT holding
+// each event at most once), which is the order of the per-event sum of the
+// host-built layouts, then the occurrence terms are applied in place.
+
+template <typename T>
+__global__ void k_pool_zero(T *__restrict__ occ, float *__restrict__ lo, int64_t catalog) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e <= catalog; e += (int64_t)gridDim.x * blockDim.x) {
+        occ[e] = T(0);
+        if (lo && e < catalog) lo[e] = 0.0f;
+    }
+}
+
+template <typename T>
+__global__ void k_pool_add(const int32_t *__restrict__ ids, const T *__restrict__ loss, int64_t n, T ret, T lim,
+                           T *__restrict__ hi, float *__restrict__ lo) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e = ids[i];
+        const T x = clamp_excess(loss[i], ret, lim);
+        if (sizeof(T) == 8) {
+            hi[e] += x;
+        } else {
+            float sum, err;
+            two_sum((float)hi[e], (float)x, sum, err);
+            hi[e] = (T)sum;
+            lo[e] += err;
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_pool_finish(T *__restrict__ occ, const float *__restrict__ lo, int64_t catalog, T occ_ret,
+                              T occ_lim) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < catalog; e += (int64_t)gridDim.x * blockDim.x) {
+        const T v = sizeof(T) == 8 ? occ[e] : (T)((float)occ[e] + lo[e]);
+        occ[e] = clamp_excess(v, occ_ret, occ_lim);
+    }
+}
+
 template <typename T>
 __global__ void k_fill_zero(T *p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -876,6 +916,32 @@ hipError_t batch_pass_t(const YetView &y, const BatchTables &b, const BatchLaunc
     return hipGetLastError();
 }
 }  // namespace
+
+namespace {
+template <typename T>
+hipError_t pool_layer_t(LayerHost &L, const Terms<T> &t, const int32_t *ids, const void *loss, const int64_t *off,
+                        const int32_t *idx, int32_t n, float *lo, hipStream_t s) {
+    T *occ = static_cast<T *>(const_cast<void *>(L.tab.occ));
+    const T *ls = static_cast<const T *>(loss);
+    const int g = cu_count() * 2;
+    hipLaunchKernelGGL((k_pool_zero<T>), dim3(g), dim3(256), 0, s, occ, lo, (int64_t)L.catalog);
+    for (int j = 0; j < n; ++j) {
+        const int64_t b = off[idx[j]], m = off[idx[j] + 1] - b;
+        if (m > 0)
+            hipLaunchKernelGGL((k_pool_add<T>), dim3(g), dim3(256), 0, s, ids + b, ls + b, m, t.ret[j], t.lim[j], occ, lo);
+    }
+    hipLaunchKernelGGL((k_pool_finish<T>), dim3(g), dim3(256), 0, s, occ, lo, (int64_t)L.catalog, t.occ_ret, t.occ_lim);
+    hipLaunchKernelGGL((k_build_filter<T>), dim3(g), dim3(256), 0, s, occ, (int64_t)L.catalog, L.tab.fshift,
+                       const_cast<uint32_t *>(L.tab.filt), L.tab.n_fwords);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_pool_layer(LayerHost &L, const int32_t *d_ids, const void *d_loss, const int64_t *h_off,
+                             const int32_t *h_idx, int32_t n, float *d_lo, hipStream_t s) {
+    if (L.precision == ARA_FP32C) return pool_layer_t<float>(L, L.t32, d_ids, d_loss, h_off, h_idx, n, d_lo, s);
+    return pool_layer_t<double>(L, L.t64, d_ids, d_loss, h_off, h_idx, n, nullptr, s);
+}
 
 hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;

@@ -1,0 +1,200 @@
+"""Serving ad hoc layer-pricing queries against a device-resident YET.
+
+A query is a new layer: some ELTs of a pool already resident on the GPU,
+with its own occurrence and aggregate terms.  Its answer is the layer's YLT
+and PML/TVaR at the requested return periods.  The paper motivates this use
+(ad hoc, real-time pricing on a portfolio, Sections I and III); the
+scheduling here is this library's own.
+
+Two servers with the same clock and the same device work per query:
+
+* ``serve_batched`` -- continuous batching.  Arrivals are admitted while the
+  pool has a free layer slot (the pool's fixed table memory is the admission
+  budget; a query that does not fit waits in the queue), and their fused
+  tables are built on the GPU on a build stream while the previous batch runs
+  on the run stream.  Whenever the run stream can take more work, everything
+  admitted and built so far (up to ARA_MAX_BATCH layers) leaves as one
+  batched pass; two batch objects alternate so the records of the next batch
+  are built while the current one runs.  PML/TVaR of a whole batch come from
+  one call.
+* ``serve_one_at_a_time`` -- the baseline: each query in arrival order is
+  built, run with the single-layer pass and reduced to PML/TVaR before the
+  next one starts.
+
+Latency of a query = time its answer is on the host - its scheduled arrival.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import ara as A
+
+
+@dataclass
+class Query:
+    qid: int
+    arrival: float          # seconds after the start of the run
+    elt_index: np.ndarray   # pool ELT indices, layer order
+    ret: np.ndarray
+    lim: np.ndarray
+    occ_ret: float
+    occ_lim: float
+    agg_ret: float
+    agg_lim: float
+    # filled by the server
+    admitted: float = -1.0
+    done: float = -1.0
+    batch_size: int = 0
+    pml: Optional[np.ndarray] = None
+    tvar: Optional[np.ndarray] = None
+    ylt: Optional[torch.Tensor] = None
+    layer: object = field(default=None, repr=False)
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def make_queries(items) -> List[Query]:
+    """Queries from (arrival, LayerSpec, pool indices) triples."""
+    out = []
+    for i, (t, spec, pick) in enumerate(items):
+        out.append(Query(i, float(t), np.asarray(pick, np.int32), np.asarray(spec.ret, np.float64),
+                         np.asarray(spec.lim, np.float64), spec.occ_ret, spec.occ_lim, spec.agg_ret, spec.agg_lim))
+    return out
+
+
+def _build(pool: A.Pool, q: Query, stream) -> A.Layer:
+    return pool.layer(q.elt_index, q.ret, q.lim, q.occ_ret, q.occ_lim, q.agg_ret, q.agg_lim, stream=stream)
+
+
+def _wait_until(clock, t):
+    while True:
+        d = t - clock()
+        if d <= 0:
+            return
+        time.sleep(min(d, 0.0005) if d > 0.0002 else 0)
+
+
+def serve_batched(yet: A.Yet, pool: A.Pool, queries: Sequence[Query], return_periods=(100.0, 250.0),
+                  max_batch: int = L.ARA_MAX_BATCH, keep_ylt: bool = False) -> dict:
+    run_s = torch.cuda.Stream()
+    build_s = torch.cuda.Stream()
+    answer_s = torch.cuda.Stream()
+    T = yet.n_trials
+    pending = collections.deque(sorted(queries, key=lambda q: q.arrival))
+    waiting: collections.deque = collections.deque()   # arrived, not admitted
+    built: List[Query] = []                           # admitted, table being built / ready
+    inflight: collections.deque = collections.deque()  # (queries, outs, event, batch slot)
+    batches = [None, None]
+    free_batch = [0, 1]
+    n_done = 0
+    n_batches = 0
+    t0 = time.perf_counter()
+    clock = lambda: time.perf_counter() - t0
+    while n_done < len(queries):
+        now = clock()
+        while pending and pending[0].arrival <= now:
+            waiting.append(pending.popleft())
+        # admission: a query enters when a layer slot (its table memory) is free
+        while waiting:
+            q = waiting[0]
+            try:
+                q.layer = _build(pool, q, build_s)
+            except L.AraError as e:
+                if e.name == "ARA_ERR_OOM":
+                    break
+                raise
+            waiting.popleft()
+            q.admitted = clock()
+            built.append(q)
+        # launch when the run stream has at most one batch queued behind the running one
+        if built and len(inflight) < 2 and free_batch:
+            group = built[:max_batch]
+            del built[:max_batch]
+            with torch.cuda.stream(run_s):
+                outs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in group]
+                if len(group) == 1:
+                    A.run_layer(yet, group[0].layer, out=outs[0], stream=run_s)
+                    slot = None
+                else:
+                    slot = free_batch.pop()
+                    layers = [q.layer for q in group]
+                    if batches[slot] is None:
+                        batches[slot] = A.Batch(yet, layers)
+                    else:
+                        batches[slot].rebuild(layers)
+                    batches[slot].run(outs, stream=run_s)
+                ev = torch.cuda.Event()
+                ev.record(run_s)
+            inflight.append((group, outs, ev, slot))
+            n_batches += 1
+        # completion, in launch order
+        if inflight and inflight[0][2].query():
+            group, outs, ev, slot = inflight.popleft()
+            answer_s.wait_event(ev)
+            pml, tvar = A.pml_tvar_many(outs, return_periods, stream=answer_s)
+            t = clock()
+            for i, q in enumerate(group):
+                q.done = t
+                q.batch_size = len(group)
+                q.pml, q.tvar = pml[i], tvar[i]
+                q.ylt = outs[i] if keep_ylt else None
+                q.layer.close()
+                q.layer = None
+            if slot is not None:
+                free_batch.append(slot)
+            n_done += len(group)
+            continue
+        if not inflight and not built and not waiting and pending:
+            _wait_until(clock, pending[0].arrival)
+        elif inflight and not waiting and (not pending or pending[0].arrival > clock()):
+            time.sleep(0.00005)
+    for b in batches:
+        if b is not None:
+            b.close()
+    return _summary(queries, n_batches)
+
+
+def serve_one_at_a_time(yet: A.Yet, pool: A.Pool, queries: Sequence[Query], return_periods=(100.0, 250.0),
+                        keep_ylt: bool = False) -> dict:
+    s = torch.cuda.Stream()
+    T = yet.n_trials
+    t0 = time.perf_counter()
+    clock = lambda: time.perf_counter() - t0
+    for q in sorted(queries, key=lambda q: q.arrival):
+        _wait_until(clock, q.arrival)
+        q.admitted = clock()
+        lay = _build(pool, q, s)
+        out = torch.empty(T, dtype=torch.float64, device="cuda")
+        A.run_layer(yet, lay, out=out, stream=s)
+        q.pml, q.tvar = (x[0] for x in A.pml_tvar_many([out], return_periods, stream=s))
+        q.done = clock()
+        q.batch_size = 1
+        q.ylt = out if keep_ylt else None
+        lay.close()
+    return _summary(queries, len(queries))
+
+
+def _pct(x: np.ndarray, p: float) -> float:
+    """Nearest-rank percentile."""
+    xs = np.sort(x)
+    k = max(1, int(np.ceil(p / 100.0 * len(xs))))
+    return float(xs[k - 1])
+
+
+def _summary(queries: Sequence[Query], n_launches: int) -> dict:
+    lat = np.array([q.latency for q in queries])
+    span = max(q.done for q in queries) - min(q.arrival for q in queries)
+    sizes = np.array([q.batch_size for q in queries])
+    return {"n_queries": len(queries), "p50_ms": _pct(lat, 50) * 1e3, "p99_ms": _pct(lat, 99) * 1e3,
+            "max_ms": float(lat.max()) * 1e3, "mean_ms": float(lat.mean()) * 1e3,
+            "layers_per_s": len(queries) / span if span > 0 else float("inf"), "launches": n_launches,
+            "mean_batch": float(sizes.mean())}

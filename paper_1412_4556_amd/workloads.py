@@ -288,7 +288,7 @@ def serving_pool(n_trials: int = 500_000, pool_size: int = 256):
 def serving_queries(pool: ElTPool, n_queries: int, rate_per_s: float, stream: int = 0):
     """Open-loop Poisson arrivals of ad hoc layer queries.
 
-    Returns a list of (arrival_time_s, LayerSpec); each query covers 1..16 ELTs
+    Returns a list of (arrival_time_s, LayerSpec, pool indices); each query covers 1..16 ELTs
     drawn without replacement from the pool, with random occurrence and
     aggregate terms drawn as in the batching workload.
     """
@@ -303,7 +303,7 @@ def serving_queries(pool: ElTPool, n_queries: int, rate_per_s: float, stream: in
         _, _, r2, l2, r3, l3 = random_layer_terms(qrng, [pool.losses[p] for p in pick])
         out.append((float(t[q]), LayerSpec([pool.ids[p] for p in pick], [pool.losses[p] for p in pick],
                                            pool.ret[pick].copy(), pool.lim[pick].copy(), r2, l2, r3, l3,
-                                           name=f"query_{q}")))
+                                           name=f"query_{q}"), pick.astype(np.int32)))
     return out
 
 
