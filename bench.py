@@ -180,6 +180,44 @@ def batch_leg(A, W, torch, n_trials, steps, precision="fp64"):
     return res
 
 
+def serving_leg(A, W, torch, n_trials, rates, max_layers=128):
+    """Poisson-arriving ad hoc layer queries (1..16 ELTs of a 256-ELT pool,
+    random occurrence/aggregate terms) against a resident YET of Poisson(1000)
+    trials: continuous batching against one query at a time."""
+    from paper_1412_4556_amd import serve as S
+
+    y, pool = W.serving_pool(n_trials)
+    log(f"serving leg: generating YET of {n_trials} Poisson(1000) trials, pool of {len(pool.ids)} ELTs")
+    ids, off = W.yet_full(y)
+    t_ids = torch.from_numpy(ids).cuda()
+    t_off = torch.from_numpy(off).cuda()
+    del ids
+    yet = A.Yet(t_ids, t_off, y.n_trials, y.catalog_size)
+    P = A.Pool(yet, pool.ids, pool.losses, "fp64", max_layers=max_layers)
+    min_batch = S.warm_up(yet, P, W.serving_queries(pool, 64, 1e6, stream=999))
+    log(f"serving leg: record pass wins from {min_batch} layers per group")
+    S.serve_one_at_a_time(yet, P, S.make_queries(W.serving_queries(pool, 10, 1e6, stream=998)))
+    out = []
+    for i, rate in enumerate(rates):
+        n = int(max(60, min(1000, rate * 3)))
+        items = W.serving_queries(pool, n, rate, stream=i)
+        b = S.serve_batched(yet, P, S.make_queries(items), min_batch=min_batch)
+        o = S.serve_one_at_a_time(yet, P, S.make_queries(items))
+        log(f"serving {rate:>6.0f}/s x {n}: batched p50 {b['p50_ms']:.2f} p99 {b['p99_ms']:.2f} ms "
+            f"{b['layers_per_s']:.0f} layers/s (mean batch {b['mean_batch']:.1f}); one-at-a-time p50 "
+            f"{o['p50_ms']:.2f} p99 {o['p99_ms']:.2f} ms {o['layers_per_s']:.0f} layers/s")
+        out.append({"rate_per_s": rate, "batched": b, "one_at_a_time": o})
+    res = {"workload": f"serving_{n_trials}_trials_pool_{len(pool.ids)}_elts", "n_trials": y.n_trials,
+           "n_events": int(off[-1]), "pool_elts": len(pool.ids), "layer_slots": max_layers,
+           "pool_device_bytes": P.device_bytes, "return_periods": [100.0, 250.0],
+           "record_pass_from_layers": min_batch, "rates": out}
+    P.close()
+    yet.close()
+    del t_ids, t_off
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +231,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-trials", type=int, default=1_000_000)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-trials", type=int, default=500_000)
+    ap.add_argument("--serving-rates", default="10,30,100,300,1000")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB 5 times (counter calibration)")
     args = ap.parse_args()
@@ -278,6 +319,11 @@ def main():
     if not args.no_batch:
         batch = batch_leg(A, W, torch, args.batch_trials, max(3, args.steps // 4))
 
+    serving = None
+    if not args.no_serving:
+        serving = serving_leg(A, W, torch, args.serving_trials,
+                              [float(r) for r in args.serving_rates.split(",") if r])
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -315,6 +361,7 @@ def main():
         "device": torch.cuda.get_device_name(0),
         "extras": extras,
         "batch": batch,
+        "serving": serving,
     }
     print(json.dumps(rec), flush=True)
 

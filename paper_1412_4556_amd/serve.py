@@ -84,7 +84,11 @@ def _wait_until(clock, t):
 
 
 def serve_batched(yet: A.Yet, pool: A.Pool, queries: Sequence[Query], return_periods=(100.0, 250.0),
-                  max_batch: int = L.ARA_MAX_BATCH, keep_ylt: bool = False) -> dict:
+                  max_batch: int = L.ARA_MAX_BATCH, min_batch: int = 2, keep_ylt: bool = False) -> dict:
+    """Continuous batching; a group of fewer than ``min_batch`` queries runs as
+    back-to-back single-layer passes (the record pass costs about the same
+    for any number of layers, so below the crossover ``warm_up`` measures it
+    loses to separate passes)."""
     run_s = torch.cuda.Stream()
     build_s = torch.cuda.Stream()
     answer_s = torch.cuda.Stream()
@@ -121,8 +125,9 @@ def serve_batched(yet: A.Yet, pool: A.Pool, queries: Sequence[Query], return_per
             del built[:max_batch]
             with torch.cuda.stream(run_s):
                 outs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in group]
-                if len(group) == 1:
-                    A.run_layer(yet, group[0].layer, out=outs[0], stream=run_s)
+                if len(group) < max(2, min_batch):
+                    for q, o in zip(group, outs):
+                        A.run_layer(yet, q.layer, out=o, stream=run_s)
                     slot = None
                 else:
                     slot = free_batch.pop()
@@ -181,6 +186,55 @@ def serve_one_at_a_time(yet: A.Yet, pool: A.Pool, queries: Sequence[Query], retu
         q.ylt = out if keep_ylt else None
         lay.close()
     return _summary(queries, len(queries))
+
+
+def warm_up(yet: A.Yet, pool: A.Pool, items, sizes=(2, 4, 8, 16, 32, 64)) -> int:
+    """First-use work outside any timed run (the batch launch shape of every
+    power-of-two batch size, tuned once per process; allocator growth), and
+    the crossover: the smallest group for which one record pass beats the
+    same number of single-layer passes.  Returns that group size."""
+    qs = make_queries(items[:max(sizes)])
+    layers = [_build(pool, q, None) for q in qs]
+    torch.cuda.synchronize()
+    T = yet.n_trials
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    one = torch.empty(T, dtype=torch.float64, device="cuda")
+    t_single = timed(lambda: A.run_layer(yet, layers[0], out=one))
+    b = None
+    t_batch = {}
+    for n in sizes:
+        if n > len(layers):
+            break
+        outs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in range(n)]
+        if b is None:
+            b = A.Batch(yet, layers[:n])
+        else:
+            b.rebuild(layers[:n])
+        t_batch[n] = timed(lambda: b.run(outs))
+        A.pml_tvar_many(outs, (100.0, 250.0))
+    torch.cuda.synchronize()
+    if b is not None:
+        b.close()
+    for l in layers:
+        l.close()
+    cross = max(sizes) + 1
+    for n in sorted(t_batch):
+        if t_batch[n] < n * t_single:
+            # first measured size that wins; interpolate down to the exact crossover
+            cross = max(2, min(n, int(np.ceil(t_batch[n] / t_single))))
+            break
+    return min(cross, L.ARA_MAX_BATCH)
 
 
 def _pct(x: np.ndarray, p: float) -> float:

@@ -93,7 +93,7 @@ def test_served_answers_same_alone_and_in_mix(prec, max_layers):
     P = A.Pool(yet, pool.ids, pool.losses, prec, max_layers=max_layers)
     items = _queries(pool, 80, 5000.0, seed=2)  # fast arrivals: batches form
     qs = S.make_queries(items)
-    summ = S.serve_batched(yet, P, qs, RPS, keep_ylt=True)
+    summ = S.serve_batched(yet, P, qs, RPS, keep_ylt=True, min_batch=2 if max_layers == 64 else 3)
     torch.cuda.synchronize()
     assert summ["n_queries"] == 80 and all(q.done >= q.arrival for q in qs)
     assert max(q.batch_size for q in qs) <= max_layers
