@@ -196,12 +196,15 @@ def serving_leg(A, W, torch, n_trials, rates, max_layers=128):
     P = A.Pool(yet, pool.ids, pool.losses, "fp64", max_layers=max_layers)
     min_batch = S.warm_up(yet, P, W.serving_queries(pool, 64, 1e6, stream=999))
     log(f"serving leg: record pass wins from {min_batch} layers per group")
-    S.serve_one_at_a_time(yet, P, S.make_queries(W.serving_queries(pool, 10, 1e6, stream=998)))
+    srv = S.BatchingServer(yet, P, min_batch=min_batch)
+    warm = W.serving_queries(pool, 40, 2000.0, stream=998)
+    srv.serve(S.make_queries(warm))
+    S.serve_one_at_a_time(yet, P, S.make_queries(warm))
     out = []
     for i, rate in enumerate(rates):
         n = int(max(60, min(1000, rate * 3)))
         items = W.serving_queries(pool, n, rate, stream=i)
-        b = S.serve_batched(yet, P, S.make_queries(items), min_batch=min_batch)
+        b = srv.serve(S.make_queries(items))
         o = S.serve_one_at_a_time(yet, P, S.make_queries(items))
         log(f"serving {rate:>6.0f}/s x {n}: batched p50 {b['p50_ms']:.2f} p99 {b['p99_ms']:.2f} ms "
             f"{b['layers_per_s']:.0f} layers/s (mean batch {b['mean_batch']:.1f}); one-at-a-time p50 "
@@ -211,6 +214,7 @@ def serving_leg(A, W, torch, n_trials, rates, max_layers=128):
            "n_events": int(off[-1]), "pool_elts": len(pool.ids), "layer_slots": max_layers,
            "pool_device_bytes": P.device_bytes, "return_periods": [100.0, 250.0],
            "record_pass_from_layers": min_batch, "rates": out}
+    srv.close()
     P.close()
     yet.close()
     del t_ids, t_off

@@ -83,89 +83,112 @@ def _wait_until(clock, t):
         time.sleep(min(d, 0.0005) if d > 0.0002 else 0)
 
 
-def serve_batched(yet: A.Yet, pool: A.Pool, queries: Sequence[Query], return_periods=(100.0, 250.0),
-                  max_batch: int = L.ARA_MAX_BATCH, min_batch: int = 2, keep_ylt: bool = False) -> dict:
-    """Continuous batching; a group of fewer than ``min_batch`` queries runs as
+class BatchingServer:
+    """Continuous-batching server over one YET and one ELT pool.  Its streams
+    and its two batch objects live as long as the server, so repeated runs
+    pay no set-up; a group of fewer than ``min_batch`` queries runs as
     back-to-back single-layer passes (the record pass costs about the same
     for any number of layers, so below the crossover ``warm_up`` measures it
     loses to separate passes)."""
-    run_s = torch.cuda.Stream()
-    build_s = torch.cuda.Stream()
-    answer_s = torch.cuda.Stream()
-    T = yet.n_trials
-    pending = collections.deque(sorted(queries, key=lambda q: q.arrival))
-    waiting: collections.deque = collections.deque()   # arrived, not admitted
-    built: List[Query] = []                           # admitted, table being built / ready
-    inflight: collections.deque = collections.deque()  # (queries, outs, event, batch slot)
-    batches = [None, None]
-    free_batch = [0, 1]
-    n_done = 0
-    n_batches = 0
-    t0 = time.perf_counter()
-    clock = lambda: time.perf_counter() - t0
-    while n_done < len(queries):
-        now = clock()
-        while pending and pending[0].arrival <= now:
-            waiting.append(pending.popleft())
-        # admission: a query enters when a layer slot (its table memory) is free
-        while waiting:
-            q = waiting[0]
-            try:
-                q.layer = _build(pool, q, build_s)
-            except L.AraError as e:
-                if e.name == "ARA_ERR_OOM":
-                    break
-                raise
-            waiting.popleft()
-            q.admitted = clock()
-            built.append(q)
-        # launch when the run stream has at most one batch queued behind the running one
-        if built and len(inflight) < 2 and free_batch:
-            group = built[:max_batch]
-            del built[:max_batch]
-            with torch.cuda.stream(run_s):
-                outs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in group]
-                if len(group) < max(2, min_batch):
-                    for q, o in zip(group, outs):
-                        A.run_layer(yet, q.layer, out=o, stream=run_s)
-                    slot = None
-                else:
-                    slot = free_batch.pop()
-                    layers = [q.layer for q in group]
-                    if batches[slot] is None:
-                        batches[slot] = A.Batch(yet, layers)
+
+    def __init__(self, yet: A.Yet, pool: A.Pool, return_periods=(100.0, 250.0), max_batch: int = L.ARA_MAX_BATCH,
+                 min_batch: int = 2):
+        self.yet, self.pool = yet, pool
+        self.return_periods = tuple(return_periods)
+        self.max_batch = int(max_batch)
+        self.min_batch = int(min_batch)
+        self.run_s = torch.cuda.Stream()
+        self.build_s = torch.cuda.Stream()
+        self.answer_s = torch.cuda.Stream()
+        self.batches = [None, None]
+
+    def close(self):
+        for b in self.batches:
+            if b is not None:
+                b.close()
+        self.batches = [None, None]
+
+    def serve(self, queries: Sequence[Query], keep_ylt: bool = False) -> dict:
+        yet, pool = self.yet, self.pool
+        run_s, build_s, answer_s = self.run_s, self.build_s, self.answer_s
+        T = yet.n_trials
+        pending = collections.deque(sorted(queries, key=lambda q: q.arrival))
+        waiting: collections.deque = collections.deque()   # arrived, not admitted
+        built: List[Query] = []                           # admitted, table being built / ready
+        inflight: collections.deque = collections.deque()  # (queries, outs, event, batch slot)
+        free_batch = [0, 1]
+        n_done = 0
+        n_launches = 0
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0
+        while n_done < len(queries):
+            now = clock()
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # admission: a query enters when a layer slot (its table memory) is free
+            while waiting:
+                q = waiting[0]
+                try:
+                    q.layer = _build(pool, q, build_s)
+                except L.AraError as e:
+                    if e.name == "ARA_ERR_OOM":
+                        break
+                    raise
+                waiting.popleft()
+                q.admitted = clock()
+                built.append(q)
+            # launch when the run stream has at most one group queued behind the running one
+            if built and len(inflight) < 2 and free_batch:
+                group = built[:self.max_batch]
+                del built[:self.max_batch]
+                with torch.cuda.stream(run_s):
+                    outs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in group]
+                    if len(group) < max(2, self.min_batch):
+                        for q, o in zip(group, outs):
+                            A.run_layer(yet, q.layer, out=o, stream=run_s)
+                        slot = None
                     else:
-                        batches[slot].rebuild(layers)
-                    batches[slot].run(outs, stream=run_s)
-                ev = torch.cuda.Event()
-                ev.record(run_s)
-            inflight.append((group, outs, ev, slot))
-            n_batches += 1
-        # completion, in launch order
-        if inflight and inflight[0][2].query():
-            group, outs, ev, slot = inflight.popleft()
-            answer_s.wait_event(ev)
-            pml, tvar = A.pml_tvar_many(outs, return_periods, stream=answer_s)
-            t = clock()
-            for i, q in enumerate(group):
-                q.done = t
-                q.batch_size = len(group)
-                q.pml, q.tvar = pml[i], tvar[i]
-                q.ylt = outs[i] if keep_ylt else None
-                q.layer.close()
-                q.layer = None
-            if slot is not None:
-                free_batch.append(slot)
-            n_done += len(group)
-            continue
-        if not inflight and not built and not waiting and pending:
-            _wait_until(clock, pending[0].arrival)
-        elif inflight and not waiting and (not pending or pending[0].arrival > clock()):
-            time.sleep(0.00005)
-    for b in batches:
-        if b is not None:
-            b.close()
-    return _summary(queries, n_batches)
+                        slot = free_batch.pop()
+                        layers = [q.layer for q in group]
+                        if self.batches[slot] is None:
+                            self.batches[slot] = A.Batch(yet, layers)
+                        else:
+                            self.batches[slot].rebuild(layers)
+                        self.batches[slot].run(outs, stream=run_s)
+                    ev = torch.cuda.Event()
+                    ev.record(run_s)
+                inflight.append((group, outs, ev, slot))
+                n_launches += 1
+            # completion, in launch order
+            if inflight and inflight[0][2].query():
+                group, outs, ev, slot = inflight.popleft()
+                answer_s.wait_event(ev)
+                pml, tvar = A.pml_tvar_many(outs, self.return_periods, stream=answer_s)
+                t = clock()
+                for i, q in enumerate(group):
+                    q.done = t
+                    q.batch_size = len(group)
+                    q.pml, q.tvar = pml[i], tvar[i]
+                    q.ylt = outs[i] if keep_ylt else None
+                    q.layer.close()
+                    q.layer = None
+                if slot is not None:
+                    free_batch.append(slot)
+                n_done += len(group)
+                continue
+            if not inflight and not built and not waiting and pending:
+                _wait_until(clock, pending[0].arrival)
+        return _summary(queries, n_launches)
+
+
+def serve_batched(yet: A.Yet, pool: A.Pool, queries: Sequence[Query], return_periods=(100.0, 250.0),
+                  max_batch: int = L.ARA_MAX_BATCH, min_batch: int = 2, keep_ylt: bool = False) -> dict:
+    """One run of a fresh BatchingServer."""
+    srv = BatchingServer(yet, pool, return_periods, max_batch, min_batch)
+    try:
+        return srv.serve(queries, keep_ylt)
+    finally:
+        srv.close()
 
 
 def serve_one_at_a_time(yet: A.Yet, pool: A.Pool, queries: Sequence[Query], return_periods=(100.0, 250.0),
