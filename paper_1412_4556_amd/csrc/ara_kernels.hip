@@ -481,6 +481,89 @@ __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int6
     }
 }
 
+// Per-event outputs with the fused layout: the loads, LDS filter and gathers
+// of k_trial_pass_fused, then, chunk by chunk, the scan of k_trial_pass_events
+// (same chunks, same lane order, same combine tree), so the outputs are
+// bitwise those of the generic per-event pass.
+template <typename T, bool FIXED, bool ALIGNED>
+__global__ __launch_bounds__(1024) void k_trial_pass_events_fused(
+    YetView y, const int64_t *__restrict__ off, const uint32_t *__restrict__ filt, int32_t n_fwords, int32_t fshift,
+    int32_t zero_slot, const T *__restrict__ occ, double agg_ret, double agg_lim, double *__restrict__ ylt,
+    double *__restrict__ cum, double *__restrict__ net) {
+    extern __shared__ uint32_t sfilt[];
+    for (int i = threadIdx.x; i < n_fwords; i += blockDim.x) sfilt[i] = filt[i];
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    constexpr int64_t kSpan = (int64_t)kGroup * 4 * kWave;
+    const int64_t last_granule = (y.n_events - 1) & ~3LL;  // launched only with n_events >= 1
+    int64_t trial = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    TrialRange r{0, 0};
+    IdGroup cur;
+    uint32_t cur_valid = 0;
+    if (trial < y.n_trials) {
+        r = fused_range<FIXED>(y, off, trial);
+        cur_valid = load_group<FIXED, ALIGNED>(y, r, chunk_start(y, r.b), lane, last_granule, cur);
+    }
+    while (trial < y.n_trials) {
+        T o[kGroup][4];
+        gather_group<T>(cur, cur_valid, sfilt, fshift, zero_slot, occ, o);
+        const int64_t next = trial + n_waves;
+        const TrialRange rn = fused_range<FIXED>(y, off, next < y.n_trials ? next : trial);
+        IdGroup nxt;
+        const uint32_t nxt_valid = load_group<FIXED, ALIGNED>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
+        Acc<T> carry = Acc<T>::zero();
+        double carry_net = 0.0;
+        int64_t base = chunk_start(y, r.b);
+        uint32_t valid = cur_valid;
+        while (true) {
+#pragma unroll
+            for (int c = 0; c < kGroup; ++c) {
+                const int64_t p = base + c * 4 * kWave + 4 * lane;
+                Acc<T> pre[4];
+                Acc<T> run = Acc<T>::zero();
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    if ((valid >> (4 * c + v)) & 1u) run.add(o[c][v]);
+                    pre[v] = run;
+                }
+                const Acc<T> incl = wave_inclusive_scan(run);
+                Acc<T> excl = shfl_acc(incl, lane > 0 ? lane - 1 : 0);
+                if (lane == 0) excl = Acc<T>::zero();
+                const Acc<T> sbase = Acc<T>::combine(carry, excl);
+                double Sv[4], Av[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    Sv[v] = Acc<T>::combine(sbase, pre[v]).value();
+                    Av[v] = clamp_excess(Sv[v], agg_ret, agg_lim);
+                }
+                double a_prev = __shfl(Av[3], lane > 0 ? lane - 1 : 0);
+                if (lane == 0) a_prev = carry_net;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    if ((valid >> (4 * c + v)) & 1u) {
+                        if (cum) cum[p + v] = Sv[v];
+                        if (net) net[p + v] = Av[v] - a_prev;
+                    }
+                    a_prev = Av[v];
+                }
+                carry = shfl_acc(Acc<T>::combine(sbase, pre[3]), kWave - 1);
+                carry_net = __shfl(Av[3], kWave - 1);
+            }
+            base += kSpan;
+            if (base >= r.e) break;
+            IdGroup more;
+            valid = load_group<FIXED, ALIGNED>(y, r, base, lane, last_granule, more);
+            gather_group<T>(more, valid, sfilt, fshift, zero_slot, occ, o);
+        }
+        if (lane == 0) ylt[trial] = clamp_excess(carry.value(), agg_ret, agg_lim);
+        trial = next;
+        r = rn;
+        cur = nxt;
+        cur_valid = nxt_valid;
+    }
+}
+
 // --------------------------------------------------------------------------------------------
 // batched pass: many layers, one read of the YET
 
@@ -792,6 +875,28 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
         const int fgrid = grid_for_trials(y.n_trials, 16, per_cu);
         hipLaunchKernelGGL(kern, dim3(fgrid), dim3(1024), lds, s, y, y.offsets, L.tab.filt, L.tab.n_fwords, L.tab.fshift,
                            L.catalog, static_cast<const T *>(L.tab.occ), t.agg_ret, t.agg_lim, d_ylt);
+        return hipGetLastError();
+    }
+    if (events && L.layout == kFused && y.n_events > 0) {
+        const size_t lds = (size_t)L.tab.n_fwords * sizeof(uint32_t);
+        const bool fixed = y.offsets == nullptr && y.aligned16 && y.events_per_trial > 0 && (y.events_per_trial % 4) == 0;
+        auto kern = fixed ? &k_trial_pass_events_fused<T, true, true>
+                          : (y.aligned16 ? &k_trial_pass_events_fused<T, false, true>
+                                         : &k_trial_pass_events_fused<T, false, false>);
+        const int variant = fixed ? 0 : (y.aligned16 ? 1 : 2);
+        static bool attr_set[2][3] = {};
+        bool &done = attr_set[sizeof(T) == 8 ? 0 : 1][variant];
+        if (!done) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kFilterBits / 8));
+            if (e != hipSuccess) return e;
+            done = true;
+        }
+        const int per_cu = lds > 80 * 1024 ? 1 : 2;
+        const int fgrid = grid_for_trials(y.n_trials, 16, per_cu);
+        hipLaunchKernelGGL(kern, dim3(fgrid), dim3(1024), lds, s, y, y.offsets, L.tab.filt, L.tab.n_fwords,
+                           L.tab.fshift, L.catalog, static_cast<const T *>(L.tab.occ), t.agg_ret, t.agg_lim, d_ylt,
+                           d_cum, d_net);
         return hipGetLastError();
     }
     if (!events) {

@@ -76,28 +76,37 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(YltPtrs ylts, long long n
         if (h[i]) atomicAdd(&hist[(yi * n_rp) * 256 + i], h[i]);
 }
 
-// one thread per selection picks the bin holding its rank, then the block
-// clears the histograms for the next pass
-__global__ void k_sel_pick(SelState *st, int n_sel, int shift, unsigned *hist) {
-    for (int s = threadIdx.x; s < n_sel; s += blockDim.x) {
+// one block per selection: the 256 bins are summed from the top in LDS and
+// the bin holding the selection's rank is picked; the histogram row is then
+// cleared for the next pass
+__global__ __launch_bounds__(256) void k_sel_pick(SelState *st, int shift, unsigned *hist) {
+    __shared__ long long suf[256];  // suf[b] = count of bins b..255
+    __shared__ int chosen;
+    const int s = blockIdx.x;
+    const int b = threadIdx.x;
+    unsigned *h = hist + (size_t)s * 256;
+    suf[b] = h[b];
+    if (b == 0) chosen = 0;  // unreachable fallback: k_rem never exceeds the candidates
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {  // inclusive suffix sum, Hillis-Steele
+        const long long add = b + d < 256 ? suf[b + d] : 0;
+        __syncthreads();
+        suf[b] += add;
+        __syncthreads();
+    }
+    const long long k_rem = st[s].k_rem;
+    const long long above = b < 255 ? suf[b + 1] : 0;  // candidates in bins above b
+    if (suf[b] >= k_rem && above < k_rem) chosen = b;  // exactly one bin satisfies this
+    __syncthreads();
+    if (b == 0) {
         SelState x = st[s];
-        long long cum = 0;
-        int chosen = 0;
-        for (int b = 255; b >= 0; --b) {
-            const long long c = hist[s * 256 + b];
-            if (cum + c >= x.k_rem) {
-                chosen = b;
-                x.k_rem -= cum;
-                break;
-            }
-            cum += c;
-        }
-        x.prefix |= ((unsigned long long)chosen) << shift;
+        const int c = chosen;
+        x.k_rem -= c < 255 ? suf[c + 1] : 0;
+        x.prefix |= ((unsigned long long)c) << shift;
         x.mask |= 255ULL << shift;
         st[s] = x;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n_sel * 256; i += blockDim.x) hist[i] = 0u;
+    h[b] = 0u;
 }
 
 // grid: (kSumBlocks, one row per YLT)
@@ -138,20 +147,29 @@ __global__ __launch_bounds__(kThreads) void k_tail_sum(YltPtrs ylts, long long n
     }
 }
 
-__global__ void k_tail_finish(const SelState *st, int n_sel, const double *psum, const unsigned long long *pcnt,
-                              double *out) {
-    for (int s = threadIdx.x; s < n_sel; s += blockDim.x) {
-        double sum = 0.0;
-        unsigned long long c = 0;
-        for (int b = 0; b < kSumBlocks; ++b) {
-            sum += psum[(size_t)s * kSumBlocks + b];
-            c += pcnt[(size_t)s * kSumBlocks + b];
+// one block per selection; the partial sums of the kSumBlocks blocks are
+// added with a fixed tree, so the result does not depend on timing
+__global__ __launch_bounds__(kSumBlocks) void k_tail_finish(const SelState *st, const double *psum,
+                                                            const unsigned long long *pcnt, double *out) {
+    __shared__ double ssum[kSumBlocks];
+    __shared__ unsigned long long scnt[kSumBlocks];
+    const int s = blockIdx.x;
+    ssum[threadIdx.x] = psum[(size_t)s * kSumBlocks + threadIdx.x];
+    scnt[threadIdx.x] = pcnt[(size_t)s * kSumBlocks + threadIdx.x];
+    __syncthreads();
+    for (int w = kSumBlocks / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            ssum[threadIdx.x] += ssum[threadIdx.x + w];
+            scnt[threadIdx.x] += scnt[threadIdx.x + w];
         }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
         const double pml = key_value(st[s].prefix);
         const long long k = st[s].k;
-        const double ties = (double)(k - (long long)c) * pml;
+        const double ties = (double)(k - (long long)scnt[0]) * pml;
         out[2 * s] = pml;
-        out[2 * s + 1] = (sum + ties) / (double)k;
+        out[2 * s + 1] = (ssum[0] + ties) / (double)k;
     }
 }
 
@@ -216,10 +234,10 @@ hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n
         const int shift = 56 - 8 * pass;
         hipLaunchKernelGGL(k_sel_hist, dim3((unsigned)gx, n_ylt), dim3(kThreads), 0, s, yp, (long long)n, st, n_rp, shift,
                            hist, nan_flag);
-        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(1024), 0, s, st, n_sel, shift, hist);
+        hipLaunchKernelGGL(k_sel_pick, dim3(n_sel), dim3(256), 0, s, st, shift, hist);
     }
     hipLaunchKernelGGL(k_tail_sum, dim3(kSumBlocks, n_ylt), dim3(kThreads), 0, s, yp, (long long)n, st, n_rp, psum, pcnt);
-    hipLaunchKernelGGL(k_tail_finish, dim3(1), dim3(1024), 0, s, st, n_sel, psum, pcnt, out);
+    hipLaunchKernelGGL(k_tail_finish, dim3(n_sel), dim3(kSumBlocks), 0, s, st, psum, pcnt, out);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::vector<double> hout(2 * (size_t)n_sel);
     int hn = 0;

@@ -141,6 +141,9 @@ def test_edge_cases(name, kw, misalign, prec):
         assert np.array_equal(ys[0], other)
     y, cum, net = gpu_layer_run(ids, off, T, C, 0, spec, prec, "fused", events=True, ids_misalign=misalign)
     assert_close_to_oracle(y, ref, prec)
+    # the fused per-event pass is bitwise the generic one (compact layout)
+    y2, cum2, net2 = gpu_layer_run(ids, off, T, C, 0, spec, prec, "compact", events=True, ids_misalign=misalign)
+    assert np.array_equal(y, y2) and np.array_equal(cum, cum2) and np.array_equal(net, net2)
     gross_ev = np.repeat(ref["gross"], np.diff(off))
     assert np.all(np.abs(cum - ref["event_cum"]) <= TOL[prec] * gross_ev)
     assert np.all(np.abs(net - ref["event_net"]) <= 2 * TOL[prec] * gross_ev)

@@ -49,3 +49,31 @@ def test_paper_scale_sampled(paper, prec, layout):
     assert np.array_equal(gp, op)
     assert np.allclose(gt, ot, rtol=1e-12, atol=0)
     lay.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_paper_scale_per_event_outputs(paper, prec):
+    """Per-event cumulative loss and aggregate-net increments at full size
+    (fused layout), on the sampled trials."""
+    wl, yet, spec, sample, ref = paper
+    lay = A.Layer(yet, spec, prec, "fused")
+    y, cum, net = A.run_layer_events(yet, lay, want_cum=True, want_net=True)
+    torch.cuda.synchronize()
+    y_plain = A.run_layer(yet, lay)
+    K = wl.yet.fixed_len
+    rows = torch.from_numpy(sample).cuda()
+    cum_s = cum.view(-1, K)[rows].cpu().numpy()
+    net_s = net.view(-1, K)[rows].cpu().numpy()
+    from paper_1412_4556_amd import workloads as W2
+    sub_ids, sub_off = W2.yet_subset(wl.yet, sample)
+    ref_ev = oracle_run(sub_ids, sub_off, len(sample), wl.yet.catalog_size, 0, spec, want_event_cum=True,
+                        want_event_net=True)
+    G = np.repeat(ref_ev["gross"], K).reshape(-1, K)
+    tol = TOL[prec]
+    assert np.all(np.abs(cum_s - ref_ev["event_cum"].reshape(-1, K)) <= tol * G)
+    assert np.all(np.abs(net_s - ref_ev["event_net"].reshape(-1, K)) <= 2 * tol * G)
+    # the year loss of the scan is the last cumulative value through the aggregate terms
+    assert_close_to_oracle(y.cpu().numpy()[sample], ref, prec)
+    assert np.allclose(net_s.sum(axis=1), y.cpu().numpy()[sample], rtol=0, atol=1e-9 * ref["gross"].max())
+    del cum, net
+    lay.close()
