@@ -700,21 +700,30 @@ __global__ __launch_bounds__(512) void k_trial_pass_batch(YetView y, const int64
         const TrialRange rn = fused_range<FIXED>(y, off, next < y.n_trials ? next : trial);
         IdGroup nxt;
         const uint32_t nxt_valid = load_group<FIXED, ALIGNED>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
+        // records double-buffered across chunks: the loads of chunk c + 1 are
+        // in flight while chunk c is added to the accumulators
         int64_t base = chunk_start(y, r.b);
         IdGroup g = cur;
         uint32_t valid = cur_valid;
+        Record<T> rr[2][4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) rr[0][v] = rec[g.id[0][v]];
         while (true) {
 #pragma unroll
             for (int c = 0; c < kGroup; ++c) {
-                Record<T> rr[4];
+                if (c + 1 < kGroup) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) rr[v] = rec[g.id[c][v]];
+                    for (int v = 0; v < 4; ++v) rr[(c + 1) & 1][v] = rec[g.id[c + 1][v]];
+                }
 #pragma unroll
-                for (int v = 0; v < 4; ++v) add_record(rr[v], ((valid >> (4 * c + v)) & 1u) != 0u, acc, lane, b);
+                for (int v = 0; v < 4; ++v)
+                    add_record(rr[c & 1][v], ((valid >> (4 * c + v)) & 1u) != 0u, acc, lane, b);
             }
             base += kSpan;
             if (base >= r.e) break;
             valid = load_group<FIXED, ALIGNED>(y, r, base, lane, last_granule, g);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) rr[0][v] = rec[g.id[0][v]];
         }
         wave_lds_fence();
         if (lane < n_layers) {
