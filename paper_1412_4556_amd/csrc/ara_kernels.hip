@@ -229,15 +229,24 @@ __device__ __forceinline__ TrialRange trial_range(const YetView &y, int64_t i) {
     return TrialRange{i * y.events_per_trial, (i + 1) * y.events_per_trial};
 }
 
+// Four consecutive event IDs from a 16-byte aligned address.  The YET is
+// read once per pass, so its loads are marked non-temporal: they do not
+// displace the layer's tables, which every trial reads again, from the caches.
+__device__ __forceinline__ int4 stream_ids4(const int32_t *p) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i v = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(p));
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+
 // Four event IDs at positions p..p+3; positions outside [b, e) read as -1.
 __device__ __forceinline__ void load4(const YetView &y, int64_t p, const TrialRange &r, int32_t id[4]) {
     if (p >= r.e) {
         id[0] = id[1] = id[2] = id[3] = -1;
     } else if (y.aligned16 && p >= r.b && p + 3 < r.e) {
-        int4 v = *reinterpret_cast<const int4 *>(y.ids + p);
+        int4 v = stream_ids4(y.ids + p);
         id[0] = v.x; id[1] = v.y; id[2] = v.z; id[3] = v.w;
     } else if (y.aligned16 && p + 3 < y.n_events) {
-        int4 v = *reinterpret_cast<const int4 *>(y.ids + p);
+        int4 v = stream_ids4(y.ids + p);
         id[0] = v.x; id[1] = v.y; id[2] = v.z; id[3] = v.w;
 #pragma unroll
         for (int v4 = 0; v4 < 4; ++v4)
@@ -361,7 +370,7 @@ __device__ __forceinline__ uint32_t load_group(const YetView &y, const TrialRang
         const int64_t p = base + c * 4 * kWave + 4 * lane;
         if (ALIGNED) {
             const int64_t q = p < last_granule ? p : last_granule;
-            const int4 v = *reinterpret_cast<const int4 *>(y.ids + q);
+            const int4 v = stream_ids4(y.ids + q);
             g.id[c][0] = v.x; g.id[c][1] = v.y; g.id[c][2] = v.z; g.id[c][3] = v.w;
             if (FIXED) {
                 valid |= (p < r.e ? 0xfu : 0u) << (4 * c);
