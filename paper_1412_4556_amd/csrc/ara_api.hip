@@ -42,6 +42,8 @@ struct ara_pool_s {
     int32_t max_layers = 0;
     int32_t fshift = 0;
     int32_t n_fwords = 0;
+    int32_t n_hwords = 0;
+    int32_t hshift = 0;
     int device = 0;
     void *d_ids = nullptr;
     void *d_loss = nullptr;
@@ -202,11 +204,27 @@ void set_terms(ara::LayerHost &h, int32_t n_elts, const double *h_ret, const dou
     h.t64.n_elts = h.t32.n_elts = n_elts;
 }
 
-void filter_geometry(int32_t C, int32_t &fshift, int32_t &n_fwords) {
+// LDS filters of the fused pass: a block filter of n_fwords words (blocks of
+// 2^fshift events) and, when blocks hold more than one event, a hashed filter
+// of n_hwords words (a power of two) in the LDS the block filter leaves free.
+void filter_geometry(int32_t C, int32_t &fshift, int32_t &n_fwords, int32_t &n_hwords, int32_t &hshift) {
     fshift = 0;
     while ((((int64_t)C + (1LL << fshift) - 1) >> fshift) > ara::kFilterBits) ++fshift;
     const int64_t n_blocks = ((int64_t)C + (1LL << fshift) - 1) >> fshift;
     n_fwords = (int32_t)((n_blocks + 31) / 32);
+    n_hwords = 0;
+    hshift = 0;
+    const int64_t room = ara::kFusedLdsBytes / 4 - n_fwords;
+    if (fshift > 0 && room >= 1) {
+        int64_t w = 1;
+        int log2_bits = 5;
+        while (w * 2 <= room) {
+            w *= 2;
+            ++log2_bits;
+        }
+        n_hwords = (int32_t)w;
+        hshift = 32 - log2_bits;
+    }
 }
 
 template <typename T>
@@ -292,8 +310,8 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
             present.reserve(rank);
             for (int64_t w = 0; w < n_words; ++w)
                 for (uint32_t x = bm[w].x; x; x &= x - 1u) present.push_back((int32_t)(w * 32 + __builtin_ctz(x)));
-            int32_t fshift = 0, n_fwords = 0;
-            filter_geometry((int32_t)C, fshift, n_fwords);
+            int32_t fshift = 0, n_fwords = 0, n_hwords = 0, hshift = 0;
+            filter_geometry((int32_t)C, fshift, n_fwords, n_hwords, hshift);
             const void *d_rows, *d_present;
             if ((st = upload(h, 0, rows.data(), rows.size(), &d_rows)) != ARA_OK) return st;
             if ((st = upload(h, 1, present.data(), present.size(), &d_present)) != ARA_OK) return st;
@@ -303,14 +321,16 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
             if (e != hipSuccess) return hip_fail(e, "device allocation of the fused table");
             h.alloc[2] = d_occ;
             h.bytes += ((size_t)C + 1) * sizeof(T);
-            e = dev_alloc(&d_filt, (size_t)n_fwords * sizeof(uint32_t));
+            e = dev_alloc(&d_filt, (size_t)(n_fwords + n_hwords) * sizeof(uint32_t));
             if (e != hipSuccess) return hip_fail(e, "device allocation of the fused filter");
             h.alloc[3] = d_filt;
-            h.bytes += (size_t)n_fwords * sizeof(uint32_t);
+            h.bytes += (size_t)(n_fwords + n_hwords) * sizeof(uint32_t);
             h.tab.occ = d_occ;
             h.tab.filt = static_cast<const uint32_t *>(d_filt);
             h.tab.fshift = fshift;
             h.tab.n_fwords = (int32_t)n_fwords;
+            h.tab.n_hwords = n_hwords;
+            h.tab.hshift = hshift;
             hipStream_t s = ara::internal_stream();
             e = ara::launch_fuse(h, d_rows, static_cast<const int32_t *>(d_present), (int64_t)rank, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -526,7 +546,7 @@ ara_status ara_create_pool(ara_yet yet, int32_t n_elts, const int32_t *h_elt_ids
     p->max_layers = max_layers;
     p->off = start;
     (void)hipGetDevice(&p->device);
-    filter_geometry(yet->catalog, p->fshift, p->n_fwords);
+    filter_geometry(yet->catalog, p->fshift, p->n_fwords, p->n_hwords, p->hshift);
     const size_t total = (size_t)start[n_elts];
     hipStream_t s = ara::internal_stream();
     hipError_t e = dev_alloc(&p->d_ids, total * sizeof(int32_t));
@@ -545,7 +565,7 @@ ara_status ara_create_pool(ara_yet yet, int32_t n_elts, const int32_t *h_elt_ids
     }
     const size_t C = (size_t)yet->catalog;
     const size_t occ_bytes = (C + 1) * (precision == ARA_FP32C ? sizeof(float) : sizeof(double));
-    const size_t filt_bytes = (size_t)p->n_fwords * sizeof(uint32_t);
+    const size_t filt_bytes = (size_t)(p->n_fwords + p->n_hwords) * sizeof(uint32_t);
     const size_t lo_bytes = precision == ARA_FP32C ? C * sizeof(float) : 0;
     p->slot_bytes = occ_bytes + filt_bytes + lo_bytes;
     p->occ.assign(max_layers, nullptr);
@@ -621,6 +641,8 @@ ara_status ara_create_layer_from_pool(ara_pool pool, int32_t n_elts, const int32
     h.tab.filt = static_cast<const uint32_t *>(pool->filt[slot]);
     h.tab.fshift = pool->fshift;
     h.tab.n_fwords = pool->n_fwords;
+    h.tab.n_hwords = pool->n_hwords;
+    h.tab.hshift = pool->hshift;
     h.bytes = pool->slot_bytes;
     set_terms(h, n_elts, h_ret, h_lim, occ_ret, occ_lim, agg_ret, agg_lim);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);

@@ -48,17 +48,26 @@ struct TablesView {
     // FUSED: occ[catalog + 1] occurrence loss of every event (occ[catalog] = 0);
     // bit b of filt[w] is
     // set iff an event of block 32w+b (a block being 2^fshift consecutive
-    // events) has a non-zero occurrence loss
+    // events) has a non-zero occurrence loss.  When fshift > 0 a second,
+    // hashed filter follows in filt[n_fwords .. n_fwords + n_hwords): bit
+    // (E * kHashMul mod 2^32) >> hshift is set for every event E with a
+    // non-zero occurrence loss (n_hwords = 0: none).
     const void *occ;
     const uint32_t *filt;
     int32_t n_fwords;
     int32_t fshift;
+    int32_t n_hwords;
+    int32_t hshift;
     int32_t catalog;
     int32_t n_words;
 };
 
-// Largest filter the fused pass keeps in LDS (bits): 128 KiB.
+// Largest block filter the fused pass keeps in LDS (bits): 128 KiB.
 constexpr int64_t kFilterBits = 1 << 20;
+// LDS of the fused pass for both filters (bytes), and the multiplier of the
+// hashed filter (2^32 / golden ratio, odd).
+constexpr int64_t kFusedLdsBytes = 160 * 1024;
+constexpr uint32_t kHashMul = 0x9E3779B1u;
 
 enum Layout : int32_t {
     kDirect = ARA_LAYOUT_DIRECT,

@@ -397,19 +397,43 @@ __device__ __forceinline__ uint32_t load_group(const YetView &y, const TrialRang
     return valid;
 }
 
-// Occurrence losses of a group: an LDS filter probe per event, then a gather
-// for every event -- of occ[E] where E's block is marked, else of the zero at
-// occ[catalog] -- so no load sits under a branch.
-template <typename T>
-__device__ __forceinline__ void gather_group(const IdGroup &g, uint32_t valid, const uint32_t *sfilt, int32_t fshift,
-                                             int32_t zero_slot, const T *__restrict__ occ, T (&o)[kGroup][4]) {
+// The fused layout's LDS filters (see TablesView): block filter words, then
+// hashed filter words.
+struct FusedFilter {
+    const uint32_t *filt;
+    int32_t n_fwords;
+    int32_t fshift;
+    int32_t n_hwords;
+    int32_t hshift;
+};
+
+__device__ __forceinline__ void load_filters(const FusedFilter &f, uint32_t *sfilt) {
+    const int n = f.n_fwords + f.n_hwords;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sfilt[i] = f.filt[i];
+    __syncthreads();
+}
+
+// Occurrence losses of a group: LDS filter probes per event, then a gather
+// for every event -- of occ[E] where E passes the filters, else of the zero
+// at occ[catalog] -- so no load sits under a branch.  The block filter has
+// no false negatives, and neither has the hashed one (HASH), so an event
+// that fails either has occ[E] = 0.
+template <typename T, bool HASH>
+__device__ __forceinline__ void gather_group(const IdGroup &g, uint32_t valid, const uint32_t *sfilt,
+                                             const FusedFilter &f, int32_t zero_slot, const T *__restrict__ occ,
+                                             T (&o)[kGroup][4]) {
+    const uint32_t *shash = sfilt + f.n_fwords;
     int32_t idx[kGroup][4];
 #pragma unroll
     for (int c = 0; c < kGroup; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const uint32_t blk = (uint32_t)g.id[c][v] >> fshift;
-            const uint32_t hit = ((valid >> (4 * c + v)) & 1u) & __builtin_amdgcn_ubfe(sfilt[blk >> 5], blk, 1u);
+            const uint32_t blk = (uint32_t)g.id[c][v] >> f.fshift;
+            uint32_t hit = ((valid >> (4 * c + v)) & 1u) & __builtin_amdgcn_ubfe(sfilt[blk >> 5], blk, 1u);
+            if (HASH) {
+                const uint32_t h = ((uint32_t)g.id[c][v] * kHashMul) >> f.hshift;
+                hit &= __builtin_amdgcn_ubfe(shash[h >> 5], h, 1u);
+            }
             idx[c][v] = hit ? g.id[c][v] : zero_slot;
         }
 #pragma unroll
@@ -441,15 +465,13 @@ __device__ __forceinline__ TrialRange fused_range(const YetView &y, const int64_
     return TrialRange{off[i], off[i + 1]};
 }
 
-template <typename T, bool FIXED, bool ALIGNED>
-__global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int64_t *__restrict__ off,
-                                                           const uint32_t *__restrict__ filt, int32_t n_fwords,
-                                                           int32_t fshift, int32_t zero_slot,
-                                                           const T *__restrict__ occ, double agg_ret, double agg_lim,
+template <typename T, bool FIXED, bool ALIGNED, bool HASH>
+__global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int64_t *__restrict__ off, FusedFilter f,
+                                                           int32_t zero_slot, const T *__restrict__ occ,
+                                                           double agg_ret, double agg_lim,
                                                            double *__restrict__ ylt) {
     extern __shared__ uint32_t sfilt[];
-    for (int i = threadIdx.x; i < n_fwords; i += blockDim.x) sfilt[i] = filt[i];
-    __syncthreads();
+    load_filters(f, sfilt);
     const int lane = lane_id();
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     constexpr int64_t kSpan = (int64_t)kGroup * 4 * kWave;
@@ -466,7 +488,7 @@ __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int6
         // gathers of this trial first, then the IDs of the next trial, so
         // that waiting for the gathers does not wait for the prefetch
         T o[kGroup][4];
-        gather_group<T>(cur, cur_valid, sfilt, fshift, zero_slot, occ, o);
+        gather_group<T, HASH>(cur, cur_valid, sfilt, f, zero_slot, occ, o);
         // the last round of a wave loads its own last trial again (unused)
         const int64_t next = trial + n_waves;
         const int64_t pre = next < y.n_trials ? next : trial;
@@ -478,7 +500,7 @@ __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int6
         for (int64_t base = chunk_start(y, r.b) + kSpan; base < r.e; base += kSpan) {
             IdGroup more;
             const uint32_t mv = load_group<FIXED, ALIGNED>(y, r, base, lane, last_granule, more);
-            gather_group<T>(more, mv, sfilt, fshift, zero_slot, occ, o);
+            gather_group<T, HASH>(more, mv, sfilt, f, zero_slot, occ, o);
             accumulate_group(o, acc);
         }
         const double S = wave_allreduce(acc).value();
@@ -494,14 +516,12 @@ __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int6
 // of k_trial_pass_fused, then, chunk by chunk, the scan of k_trial_pass_events
 // (same chunks, same lane order, same combine tree), so the outputs are
 // bitwise those of the generic per-event pass.
-template <typename T, bool FIXED, bool ALIGNED>
+template <typename T, bool FIXED, bool ALIGNED, bool HASH>
 __global__ __launch_bounds__(1024) void k_trial_pass_events_fused(
-    YetView y, const int64_t *__restrict__ off, const uint32_t *__restrict__ filt, int32_t n_fwords, int32_t fshift,
-    int32_t zero_slot, const T *__restrict__ occ, double agg_ret, double agg_lim, double *__restrict__ ylt,
-    double *__restrict__ cum, double *__restrict__ net) {
+    YetView y, const int64_t *__restrict__ off, FusedFilter f, int32_t zero_slot, const T *__restrict__ occ,
+    double agg_ret, double agg_lim, double *__restrict__ ylt, double *__restrict__ cum, double *__restrict__ net) {
     extern __shared__ uint32_t sfilt[];
-    for (int i = threadIdx.x; i < n_fwords; i += blockDim.x) sfilt[i] = filt[i];
-    __syncthreads();
+    load_filters(f, sfilt);
     const int lane = lane_id();
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     constexpr int64_t kSpan = (int64_t)kGroup * 4 * kWave;
@@ -516,7 +536,7 @@ __global__ __launch_bounds__(1024) void k_trial_pass_events_fused(
     }
     while (trial < y.n_trials) {
         T o[kGroup][4];
-        gather_group<T>(cur, cur_valid, sfilt, fshift, zero_slot, occ, o);
+        gather_group<T, HASH>(cur, cur_valid, sfilt, f, zero_slot, occ, o);
         const int64_t next = trial + n_waves;
         const TrialRange rn = fused_range<FIXED>(y, off, next < y.n_trials ? next : trial);
         IdGroup nxt;
@@ -563,7 +583,7 @@ __global__ __launch_bounds__(1024) void k_trial_pass_events_fused(
             if (base >= r.e) break;
             IdGroup more;
             valid = load_group<FIXED, ALIGNED>(y, r, base, lane, last_granule, more);
-            gather_group<T>(more, valid, sfilt, fshift, zero_slot, occ, o);
+            gather_group<T, HASH>(more, valid, sfilt, f, zero_slot, occ, o);
         }
         if (lane == 0) ylt[trial] = clamp_excess(carry.value(), agg_ret, agg_lim);
         trial = next;
@@ -834,6 +854,17 @@ __global__ void k_build_filter(const T *__restrict__ occ, int64_t catalog, int32
     }
 }
 
+// Hashed filter: bit (E * kHashMul) >> hshift for every event E with a
+// non-zero occurrence loss (words cleared beforehand).
+template <typename T>
+__global__ void k_hash_filter(const T *__restrict__ occ, int64_t catalog, int32_t hshift, uint32_t *__restrict__ words) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < catalog; e += (int64_t)gridDim.x * blockDim.x)
+        if (occ[e] != T(0)) {
+            const uint32_t h = ((uint32_t)e * kHashMul) >> hshift;
+            atomicOr(&words[h >> 5], 1u << (h & 31u));
+        }
+}
+
 __global__ void k_validate_yet(const int32_t *__restrict__ ids, int64_t n, int32_t catalog,
                                const int64_t *__restrict__ off, int64_t n_trials, int32_t *flags) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -875,46 +906,43 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
     if (y.n_trials == 0) return hipSuccess;
     const int grid = grid_for_trials(y.n_trials, 4, 8);
     const dim3 blk(256);
-    if (!events && L.layout == kFused && y.n_events > 0) {
-        const size_t lds = (size_t)L.tab.n_fwords * sizeof(uint32_t);
+    if (L.layout == kFused && y.n_events > 0) {
+        const FusedFilter f{L.tab.filt, L.tab.n_fwords, L.tab.fshift, L.tab.n_hwords, L.tab.hshift};
+        const size_t lds = (size_t)(f.n_fwords + f.n_hwords) * sizeof(uint32_t);
+        if (lds > (size_t)kFusedLdsBytes) return hipErrorInvalidValue;
         const bool fixed = y.offsets == nullptr && y.aligned16 && y.events_per_trial > 0 && (y.events_per_trial % 4) == 0;
-        auto kern = fixed ? &k_trial_pass_fused<T, true, true>
-                          : (y.aligned16 ? &k_trial_pass_fused<T, false, true> : &k_trial_pass_fused<T, false, false>);
-        const int variant = fixed ? 0 : (y.aligned16 ? 1 : 2);
-        static bool attr_set[2][3] = {};
-        bool &done = attr_set[sizeof(T) == 8 ? 0 : 1][variant];
+        const bool hash = f.n_hwords > 0;
+        const int variant = (fixed ? 0 : (y.aligned16 ? 1 : 2)) + (hash ? 3 : 0);
+        using PassK = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const T *, double, double, double *);
+        using EventsK = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const T *, double, double, double *,
+                                 double *, double *);
+        const PassK pk[6] = {&k_trial_pass_fused<T, true, true, false>,  &k_trial_pass_fused<T, false, true, false>,
+                             &k_trial_pass_fused<T, false, false, false>, &k_trial_pass_fused<T, true, true, true>,
+                             &k_trial_pass_fused<T, false, true, true>,   &k_trial_pass_fused<T, false, false, true>};
+        const EventsK ek[6] = {&k_trial_pass_events_fused<T, true, true, false>,
+                               &k_trial_pass_events_fused<T, false, true, false>,
+                               &k_trial_pass_events_fused<T, false, false, false>,
+                               &k_trial_pass_events_fused<T, true, true, true>,
+                               &k_trial_pass_events_fused<T, false, true, true>,
+                               &k_trial_pass_events_fused<T, false, false, true>};
+        const void *kern = events ? reinterpret_cast<const void *>(ek[variant]) : reinterpret_cast<const void *>(pk[variant]);
+        static bool attr_set[2][2][6] = {};
+        bool &done = attr_set[sizeof(T) == 8 ? 0 : 1][events ? 1 : 0][variant];
         if (!done) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kFilterBits / 8));
+            hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsBytes);
             if (e != hipSuccess) return e;
             done = true;
         }
-        const int per_cu = lds > 80 * 1024 ? 1 : 2;
+        const int per_cu = lds > (size_t)kFusedLdsBytes / 2 ? 1 : 2;
         const int fgrid = grid_for_trials(y.n_trials, 16, per_cu);
-        hipLaunchKernelGGL(kern, dim3(fgrid), dim3(1024), lds, s, y, y.offsets, L.tab.filt, L.tab.n_fwords, L.tab.fshift,
-                           L.catalog, static_cast<const T *>(L.tab.occ), t.agg_ret, t.agg_lim, d_ylt);
-        return hipGetLastError();
-    }
-    if (events && L.layout == kFused && y.n_events > 0) {
-        const size_t lds = (size_t)L.tab.n_fwords * sizeof(uint32_t);
-        const bool fixed = y.offsets == nullptr && y.aligned16 && y.events_per_trial > 0 && (y.events_per_trial % 4) == 0;
-        auto kern = fixed ? &k_trial_pass_events_fused<T, true, true>
-                          : (y.aligned16 ? &k_trial_pass_events_fused<T, false, true>
-                                         : &k_trial_pass_events_fused<T, false, false>);
-        const int variant = fixed ? 0 : (y.aligned16 ? 1 : 2);
-        static bool attr_set[2][3] = {};
-        bool &done = attr_set[sizeof(T) == 8 ? 0 : 1][variant];
-        if (!done) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kFilterBits / 8));
-            if (e != hipSuccess) return e;
-            done = true;
+        const T *occ = static_cast<const T *>(L.tab.occ);
+        if (!events) {
+            hipLaunchKernelGGL(pk[variant], dim3(fgrid), dim3(1024), lds, s, y, y.offsets, f, L.catalog, occ, t.agg_ret,
+                               t.agg_lim, d_ylt);
+        } else {
+            hipLaunchKernelGGL(ek[variant], dim3(fgrid), dim3(1024), lds, s, y, y.offsets, f, L.catalog, occ, t.agg_ret,
+                               t.agg_lim, d_ylt, d_cum, d_net);
         }
-        const int per_cu = lds > 80 * 1024 ? 1 : 2;
-        const int fgrid = grid_for_trials(y.n_trials, 16, per_cu);
-        hipLaunchKernelGGL(kern, dim3(fgrid), dim3(1024), lds, s, y, y.offsets, L.tab.filt, L.tab.n_fwords,
-                           L.tab.fshift, L.catalog, static_cast<const T *>(L.tab.occ), t.agg_ret, t.agg_lim, d_ylt,
-                           d_cum, d_net);
         return hipGetLastError();
     }
     if (!events) {
@@ -970,6 +998,11 @@ hipError_t fuse_t(LayerHost &L, const Terms<T> &t, const void *d_rows, const int
                            t, occ);
     hipLaunchKernelGGL((k_build_filter<T>), dim3(g), dim3(256), 0, s, occ, (int64_t)L.catalog, L.tab.fshift,
                        const_cast<uint32_t *>(L.tab.filt), L.tab.n_fwords);
+    if (L.tab.n_hwords > 0) {
+        uint32_t *hw = const_cast<uint32_t *>(L.tab.filt) + L.tab.n_fwords;
+        hipLaunchKernelGGL((k_fill_zero<uint32_t>), dim3(g), dim3(256), 0, s, hw, (int64_t)L.tab.n_hwords);
+        hipLaunchKernelGGL((k_hash_filter<T>), dim3(g), dim3(256), 0, s, occ, (int64_t)L.catalog, L.tab.hshift, hw);
+    }
     return hipGetLastError();
 }
 }  // namespace
@@ -1056,6 +1089,11 @@ hipError_t pool_layer_t(LayerHost &L, const Terms<T> &t, const int32_t *ids, con
     hipLaunchKernelGGL((k_pool_finish<T>), dim3(g), dim3(256), 0, s, occ, lo, (int64_t)L.catalog, t.occ_ret, t.occ_lim);
     hipLaunchKernelGGL((k_build_filter<T>), dim3(g), dim3(256), 0, s, occ, (int64_t)L.catalog, L.tab.fshift,
                        const_cast<uint32_t *>(L.tab.filt), L.tab.n_fwords);
+    if (L.tab.n_hwords > 0) {
+        uint32_t *hw = const_cast<uint32_t *>(L.tab.filt) + L.tab.n_fwords;
+        hipLaunchKernelGGL((k_fill_zero<uint32_t>), dim3(g), dim3(256), 0, s, hw, (int64_t)L.tab.n_hwords);
+        hipLaunchKernelGGL((k_hash_filter<T>), dim3(g), dim3(256), 0, s, occ, (int64_t)L.catalog, L.tab.hshift, hw);
+    }
     return hipGetLastError();
 }
 }  // namespace

@@ -126,6 +126,12 @@ EDGE = [
     ("open_terms", dict(seed=39, n_trials=300, mean_len=100.0, catalog=3000, n_elts=4, elt_size=800, terms="open"), False),
     ("counting", dict(seed=40, n_trials=300, mean_len=100.0, catalog=3000, n_elts=4, elt_size=800, terms="counting",
                       integer_losses=True), False),
+    # catalogues above 2^20 events: the fused pass's block filter covers
+    # several events per bit and a hashed filter is probed as well
+    ("hashed_filter_1.1M", dict(seed=44, n_trials=1500, mean_len=400.0, catalog=1_100_000, n_elts=6, elt_size=40_000),
+     False),
+    ("hashed_filter_3M_misaligned", dict(seed=45, n_trials=1200, mean_len=350.0, catalog=3_000_000, n_elts=8,
+                                         elt_size=60_000), True),
 ]
 
 
@@ -164,6 +170,22 @@ def test_fixed_length_trials(K, misalign):
               for lay in ("compact", "fused")]
         assert_close_to_oracle(ys[0], ref, prec)
         assert np.array_equal(ys[0], ys[1])
+
+
+def test_fixed_length_large_catalog():
+    """The paper's shape at 3,000 trials: 1,000 events per trial (no offsets
+    array), a 2,000,000-event catalogue and 16 ELTs of 20,000 events, so the
+    fixed-length fused pass runs with both LDS filters."""
+    T, K, C = 3000, 1000, 2_000_000
+    rng = np.random.default_rng(46)
+    ids = rng.integers(0, C, size=T * K, dtype=np.int32)
+    _, _, spec = W.random_case(46, 1, 1.0, C, 16, 20_000)
+    ref = oracle_run(ids, None, T, C, K, spec)
+    for prec in PRECS:
+        ys = [gpu_layer_run(ids, None, T, C, K, spec, prec, lay) for lay in ("compact", "fused")]
+        assert_close_to_oracle(ys[0], ref, prec)
+        assert np.array_equal(ys[0], ys[1])
+        assert (ys[1] > 0).mean() > 0.05
 
 
 @pytest.mark.parametrize("prec", PRECS)
