@@ -348,28 +348,34 @@ __global__ __launch_bounds__(256) void k_trial_pass_events(YetView y, TablesView
 #endif
 constexpr int kGroup = ARA_FUSED_GROUP;
 
-struct IdGroup {
-    int32_t id[kGroup][4];
+template <int G>
+struct IdGroupT {
+    int32_t id[G][4];
 };
+using IdGroup = IdGroupT<kGroup>;
 
 // ID loads of the fused pass.  With a 16-byte aligned YET every lane issues
-// its kGroup 16-byte loads unconditionally (a conditional load makes the
-// compiler wait for it inside the branch, which serialises the loads): the
-// address is clamped to the last 16-byte granule that holds a YET element, so
-// a load never leaves the granules of the buffer, and positions outside the
-// trial are masked afterwards (their IDs replaced by 0).
+// its G 16-byte loads unconditionally (a conditional load makes the compiler
+// wait for it inside the branch, which serialises the loads): the address is
+// clamped to the trial's last 16-byte granule (for an empty trial and for
+// FIXED, the YET's last one), so a lane past the end of its trial reads a
+// line the wave has read already instead of the next trial's IDs, and
+// positions outside the trial are masked afterwards (their IDs replaced by 0).
 //   FIXED: every trial holds the same non-zero multiple of 4 events, so a
 //          lane's four IDs are wholly inside or wholly past the trial.
 //   !ALIGNED: element loads with bounds checks (slow path, any alignment).
-template <bool FIXED, bool ALIGNED>
+template <bool FIXED, bool ALIGNED, int G = kGroup>
 __device__ __forceinline__ uint32_t load_group(const YetView &y, const TrialRange &r, int64_t base, int lane,
-                                               int64_t last_granule, IdGroup &g) {
+                                               int64_t last_granule, IdGroupT<G> &g) {
     uint32_t valid = 0;  // bit 4c+v: element v of chunk c lies in the trial
+    // (FIXED: a trial ends on a granule boundary; the YET-wide clamp costs
+    // at most one granule per lane and no extra registers)
+    const int64_t lim = (FIXED || r.e <= r.b) ? last_granule : ((r.e - 1) & ~3LL);
 #pragma unroll
-    for (int c = 0; c < kGroup; ++c) {
+    for (int c = 0; c < G; ++c) {
         const int64_t p = base + c * 4 * kWave + 4 * lane;
         if (ALIGNED) {
-            const int64_t q = p < last_granule ? p : last_granule;
+            const int64_t q = p < lim ? p : lim;
             const int4 v = stream_ids4(y.ids + q);
             g.id[c][0] = v.x; g.id[c][1] = v.y; g.id[c][2] = v.z; g.id[c][3] = v.w;
             if (FIXED) {
@@ -418,14 +424,14 @@ __device__ __forceinline__ void load_filters(const FusedFilter &f, uint32_t *sfi
 // at occ[catalog] -- so no load sits under a branch.  The block filter has
 // no false negatives, and neither has the hashed one (HASH), so an event
 // that fails either has occ[E] = 0.
-template <typename T, bool HASH>
-__device__ __forceinline__ void gather_group(const IdGroup &g, uint32_t valid, const uint32_t *sfilt,
+template <typename T, bool HASH, int G = kGroup>
+__device__ __forceinline__ void gather_group(const IdGroupT<G> &g, uint32_t valid, const uint32_t *sfilt,
                                              const FusedFilter &f, int32_t zero_slot, const T *__restrict__ occ,
-                                             T (&o)[kGroup][4]) {
+                                             T (&o)[G][4]) {
     const uint32_t *shash = sfilt + f.n_fwords;
-    int32_t idx[kGroup][4];
+    int32_t idx[G][4];
 #pragma unroll
-    for (int c = 0; c < kGroup; ++c)
+    for (int c = 0; c < G; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const uint32_t blk = (uint32_t)g.id[c][v] >> f.fshift;
@@ -437,16 +443,16 @@ __device__ __forceinline__ void gather_group(const IdGroup &g, uint32_t valid, c
             idx[c][v] = hit ? g.id[c][v] : zero_slot;
         }
 #pragma unroll
-    for (int c = 0; c < kGroup; ++c)
+    for (int c = 0; c < G; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v) o[c][v] = occ[idx[c][v]];
 }
 
 // Adds in k_trial_pass order; adding an exact zero changes no bit of the sum.
-template <typename T>
-__device__ __forceinline__ void accumulate_group(const T (&o)[kGroup][4], Acc<T> &acc) {
+template <typename T, int G = kGroup>
+__device__ __forceinline__ void accumulate_group(const T (&o)[G][4], Acc<T> &acc) {
 #pragma unroll
-    for (int c = 0; c < kGroup; ++c)
+    for (int c = 0; c < G; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             if (sizeof(T) == 8) {
@@ -465,7 +471,7 @@ __device__ __forceinline__ TrialRange fused_range(const YetView &y, const int64_
     return TrialRange{off[i], off[i + 1]};
 }
 
-template <typename T, bool FIXED, bool ALIGNED, bool HASH>
+template <typename T, bool FIXED, bool ALIGNED, bool HASH, int G>
 __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int64_t *__restrict__ off, FusedFilter f,
                                                            int32_t zero_slot, const T *__restrict__ occ,
                                                            double agg_ret, double agg_lim,
@@ -474,33 +480,33 @@ __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int6
     load_filters(f, sfilt);
     const int lane = lane_id();
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    constexpr int64_t kSpan = (int64_t)kGroup * 4 * kWave;
+    constexpr int64_t kSpan = (int64_t)G * 4 * kWave;
     const int64_t last_granule = (y.n_events - 1) & ~3LL;  // launched only with n_events >= 1
     int64_t trial = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     TrialRange r{0, 0};
-    IdGroup cur;
+    IdGroupT<G> cur;
     uint32_t cur_valid = 0;
     if (trial < y.n_trials) {
         r = fused_range<FIXED>(y, off, trial);
-        cur_valid = load_group<FIXED, ALIGNED>(y, r, chunk_start(y, r.b), lane, last_granule, cur);
+        cur_valid = load_group<FIXED, ALIGNED, G>(y, r, chunk_start(y, r.b), lane, last_granule, cur);
     }
     while (trial < y.n_trials) {
         // gathers of this trial first, then the IDs of the next trial, so
         // that waiting for the gathers does not wait for the prefetch
-        T o[kGroup][4];
-        gather_group<T, HASH>(cur, cur_valid, sfilt, f, zero_slot, occ, o);
+        T o[G][4];
+        gather_group<T, HASH, G>(cur, cur_valid, sfilt, f, zero_slot, occ, o);
         // the last round of a wave loads its own last trial again (unused)
         const int64_t next = trial + n_waves;
         const int64_t pre = next < y.n_trials ? next : trial;
         const TrialRange rn = fused_range<FIXED>(y, off, pre);
-        IdGroup nxt;
-        const uint32_t nxt_valid = load_group<FIXED, ALIGNED>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
+        IdGroupT<G> nxt;
+        const uint32_t nxt_valid = load_group<FIXED, ALIGNED, G>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
         Acc<T> acc = Acc<T>::zero();
         accumulate_group(o, acc);
         for (int64_t base = chunk_start(y, r.b) + kSpan; base < r.e; base += kSpan) {
-            IdGroup more;
-            const uint32_t mv = load_group<FIXED, ALIGNED>(y, r, base, lane, last_granule, more);
-            gather_group<T, HASH>(more, mv, sfilt, f, zero_slot, occ, o);
+            IdGroupT<G> more;
+            const uint32_t mv = load_group<FIXED, ALIGNED, G>(y, r, base, lane, last_granule, more);
+            gather_group<T, HASH, G>(more, mv, sfilt, f, zero_slot, occ, o);
             accumulate_group(o, acc);
         }
         const double S = wave_allreduce(acc).value();
@@ -516,7 +522,7 @@ __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int6
 // of k_trial_pass_fused, then, chunk by chunk, the scan of k_trial_pass_events
 // (same chunks, same lane order, same combine tree), so the outputs are
 // bitwise those of the generic per-event pass.
-template <typename T, bool FIXED, bool ALIGNED, bool HASH>
+template <typename T, bool FIXED, bool ALIGNED, bool HASH, int G>
 __global__ __launch_bounds__(1024) void k_trial_pass_events_fused(
     YetView y, const int64_t *__restrict__ off, FusedFilter f, int32_t zero_slot, const T *__restrict__ occ,
     double agg_ret, double agg_lim, double *__restrict__ ylt, double *__restrict__ cum, double *__restrict__ net) {
@@ -524,30 +530,30 @@ __global__ __launch_bounds__(1024) void k_trial_pass_events_fused(
     load_filters(f, sfilt);
     const int lane = lane_id();
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    constexpr int64_t kSpan = (int64_t)kGroup * 4 * kWave;
+    constexpr int64_t kSpan = (int64_t)G * 4 * kWave;
     const int64_t last_granule = (y.n_events - 1) & ~3LL;  // launched only with n_events >= 1
     int64_t trial = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     TrialRange r{0, 0};
-    IdGroup cur;
+    IdGroupT<G> cur;
     uint32_t cur_valid = 0;
     if (trial < y.n_trials) {
         r = fused_range<FIXED>(y, off, trial);
-        cur_valid = load_group<FIXED, ALIGNED>(y, r, chunk_start(y, r.b), lane, last_granule, cur);
+        cur_valid = load_group<FIXED, ALIGNED, G>(y, r, chunk_start(y, r.b), lane, last_granule, cur);
     }
     while (trial < y.n_trials) {
-        T o[kGroup][4];
-        gather_group<T, HASH>(cur, cur_valid, sfilt, f, zero_slot, occ, o);
+        T o[G][4];
+        gather_group<T, HASH, G>(cur, cur_valid, sfilt, f, zero_slot, occ, o);
         const int64_t next = trial + n_waves;
         const TrialRange rn = fused_range<FIXED>(y, off, next < y.n_trials ? next : trial);
-        IdGroup nxt;
-        const uint32_t nxt_valid = load_group<FIXED, ALIGNED>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
+        IdGroupT<G> nxt;
+        const uint32_t nxt_valid = load_group<FIXED, ALIGNED, G>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
         Acc<T> carry = Acc<T>::zero();
         double carry_net = 0.0;
         int64_t base = chunk_start(y, r.b);
         uint32_t valid = cur_valid;
         while (true) {
 #pragma unroll
-            for (int c = 0; c < kGroup; ++c) {
+            for (int c = 0; c < G; ++c) {
                 const int64_t p = base + c * 4 * kWave + 4 * lane;
                 Acc<T> pre[4];
                 Acc<T> run = Acc<T>::zero();
@@ -581,9 +587,9 @@ __global__ __launch_bounds__(1024) void k_trial_pass_events_fused(
             }
             base += kSpan;
             if (base >= r.e) break;
-            IdGroup more;
-            valid = load_group<FIXED, ALIGNED>(y, r, base, lane, last_granule, more);
-            gather_group<T, HASH>(more, valid, sfilt, f, zero_slot, occ, o);
+            IdGroupT<G> more;
+            valid = load_group<FIXED, ALIGNED, G>(y, r, base, lane, last_granule, more);
+            gather_group<T, HASH, G>(more, valid, sfilt, f, zero_slot, occ, o);
         }
         if (lane == 0) ylt[trial] = clamp_excess(carry.value(), agg_ret, agg_lim);
         trial = next;
@@ -912,21 +918,28 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
         if (lds > (size_t)kFusedLdsBytes) return hipErrorInvalidValue;
         const bool fixed = y.offsets == nullptr && y.aligned16 && y.events_per_trial > 0 && (y.events_per_trial % 4) == 0;
         const bool hash = f.n_hwords > 0;
-        const int variant = (fixed ? 0 : (y.aligned16 ? 1 : 2)) + (hash ? 3 : 0);
+        // ragged aligned YETs of long trials take five-chunk groups (1,280
+        // events) in the YLT pass, so a Poisson(1000) trial rarely needs a
+        // second group (the per-event pass has no registers to spare for it)
+        const bool wide = !events && !fixed && y.aligned16 && y.n_trials > 0 && y.n_events / y.n_trials > 768;
+        const int variant = wide ? (hash ? 7 : 6) : (fixed ? 0 : (y.aligned16 ? 1 : 2)) + (hash ? 3 : 0);
         using PassK = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const T *, double, double, double *);
         using EventsK = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const T *, double, double, double *,
                                  double *, double *);
-        const PassK pk[6] = {&k_trial_pass_fused<T, true, true, false>,  &k_trial_pass_fused<T, false, true, false>,
-                             &k_trial_pass_fused<T, false, false, false>, &k_trial_pass_fused<T, true, true, true>,
-                             &k_trial_pass_fused<T, false, true, true>,   &k_trial_pass_fused<T, false, false, true>};
-        const EventsK ek[6] = {&k_trial_pass_events_fused<T, true, true, false>,
-                               &k_trial_pass_events_fused<T, false, true, false>,
-                               &k_trial_pass_events_fused<T, false, false, false>,
-                               &k_trial_pass_events_fused<T, true, true, true>,
-                               &k_trial_pass_events_fused<T, false, true, true>,
-                               &k_trial_pass_events_fused<T, false, false, true>};
+        const PassK pk[8] = {&k_trial_pass_fused<T, true, true, false, 4>,   &k_trial_pass_fused<T, false, true, false, 4>,
+                             &k_trial_pass_fused<T, false, false, false, 4>, &k_trial_pass_fused<T, true, true, true, 4>,
+                             &k_trial_pass_fused<T, false, true, true, 4>,   &k_trial_pass_fused<T, false, false, true, 4>,
+                             &k_trial_pass_fused<T, false, true, false, 5>,  &k_trial_pass_fused<T, false, true, true, 5>};
+        const EventsK ek[8] = {&k_trial_pass_events_fused<T, true, true, false, 4>,
+                               &k_trial_pass_events_fused<T, false, true, false, 4>,
+                               &k_trial_pass_events_fused<T, false, false, false, 4>,
+                               &k_trial_pass_events_fused<T, true, true, true, 4>,
+                               &k_trial_pass_events_fused<T, false, true, true, 4>,
+                               &k_trial_pass_events_fused<T, false, false, true, 4>,
+                               nullptr,
+                               nullptr};
         const void *kern = events ? reinterpret_cast<const void *>(ek[variant]) : reinterpret_cast<const void *>(pk[variant]);
-        static bool attr_set[2][2][6] = {};
+        static bool attr_set[2][2][8] = {};
         bool &done = attr_set[sizeof(T) == 8 ? 0 : 1][events ? 1 : 0][variant];
         if (!done) {
             hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsBytes);
