@@ -237,7 +237,7 @@ def main():
     ap.add_argument("--batch-trials", type=int, default=1_000_000)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-trials", type=int, default=500_000)
-    ap.add_argument("--serving-rates", default="10,30,100,300,1000")
+    ap.add_argument("--serving-rates", default="10,30,100,300,1000,3000")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB 5 times (counter calibration)")
     args = ap.parse_args()
