@@ -27,6 +27,12 @@
  *   the part of the aggregate-net loss attributed to the k-th event, which
  *   is the quantity that depends on the order of prior events; the other
  *   optional per-event output is S itself after each event.
+ *   The optional per-trial output occ_max is the largest occurrence loss o
+ *   of the trial (0 for an empty trial): the loss on an occurrence basis,
+ *   from which occurrence-basis PML/TVaR and return period losses follow
+ *   the same way as from the YLT (the paper names return period losses
+ *   among the reports derived from the analysis, Section III; the
+ *   occurrence basis is a reading, see the design notes).
  *
  * Readings of points the paper leaves open are listed in the design notes:
  * the max(., 0) missing an argument in the printed FT2/FT3 formulas, the
@@ -71,7 +77,8 @@ int oracle_run_layer(const int32_t *event_ids,      /* [n_events] */
                      double *occ_sum,               /* [n_trials] S before FT3, or NULL */
                      double *gross,                 /* [n_trials] sum of looked-up losses, or NULL */
                      double *event_cum,             /* [n_events] S after event k, or NULL */
-                     double *event_net)             /* [n_events] A_k - A_{k-1}, or NULL */
+                     double *event_net,             /* [n_events] A_k - A_{k-1}, or NULL */
+                     double *occ_max)               /* [n_trials] largest o of the trial, or NULL */
 {
     if (n_trials < 0 || n_elts < 0 || catalog_size < 0) return -1;
     if (!offsets && events_per_trial < 0) return -1;
@@ -106,7 +113,7 @@ int oracle_run_layer(const int32_t *event_ids,      /* [n_events] */
     for (int64_t i = 0; i < n_trials; ++i) {
         int64_t begin = offsets ? offsets[i] : i * events_per_trial;
         int64_t end = offsets ? offsets[i + 1] : (i + 1) * events_per_trial;
-        double S = 0.0, G = 0.0, A_prev = 0.0;
+        double S = 0.0, G = 0.0, A_prev = 0.0, M = 0.0;
         for (int64_t k = begin; k < end; ++k) {
             int32_t E = event_ids[k];
             if (E < 0 || (size_t)E >= C) { bad = 1; break; }
@@ -119,6 +126,7 @@ int oracle_run_layer(const int32_t *event_ids,      /* [n_events] */
             }
             /* step 3: occurrence terms */
             double o = clamp_excess(e, occ_ret, occ_lim);
+            if (o > M) M = o;
             /* step 4: cumulative sum within the trial, aggregate terms */
             S += o;
             if (event_cum) event_cum[k] = S;
@@ -131,9 +139,10 @@ int oracle_run_layer(const int32_t *event_ids,      /* [n_events] */
         ylt[i] = clamp_excess(S, agg_ret, agg_lim);
         if (occ_sum) occ_sum[i] = S;
         if (gross) gross[i] = G;
+        if (occ_max) occ_max[i] = M;
     }
     free(table);
     return bad ? -2 : 0;
 }
 
-int oracle_version(void) { return 1; }
+int oracle_version(void) { return 2; }

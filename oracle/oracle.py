@@ -45,7 +45,7 @@ def load_library(path: str):
     P = ctypes.c_void_p
     i64, i32, d = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     lib.oracle_run_layer.argtypes = [P, P, i64, i64, i32, i32, P, P, P, P, P, d, d, d, d, ctypes.c_int,
-                                     P, P, P, P, P]
+                                     P, P, P, P, P, P]
     lib.oracle_run_layer.restype = ctypes.c_int
     return lib
 
@@ -69,14 +69,15 @@ class OracleError(RuntimeError):
 
 def run_layer(ids: np.ndarray, offsets: Optional[np.ndarray], n_trials: int, events_per_trial: int,
               catalog_size: int, layer, n_threads: int = 1, want_event_net: bool = False, lib=None,
-              want_event_cum: bool = False):
+              want_event_cum: bool = False, want_occ_max: bool = False):
     """Run one layer over a YET.
 
     Returns a dict with ``ylt`` (year loss per trial), ``occ_sum`` (the
     cumulative occurrence loss S before the aggregate terms), ``gross`` (sum of
     every looked-up loss before any term, used as the error scale) and, if
     asked, ``event_net`` (per-event increments of the aggregate-net loss) and
-    ``event_cum`` (the cumulative occurrence loss S after each event).
+    ``event_cum`` (the cumulative occurrence loss S after each event) and
+    ``occ_max`` (the largest occurrence loss of each trial, 0 if empty).
     """
     lib = _load() if lib is None else lib
     ids = np.ascontiguousarray(ids, dtype=np.int32)
@@ -92,10 +93,11 @@ def run_layer(ids: np.ndarray, offsets: Optional[np.ndarray], n_trials: int, eve
     gross = np.zeros(n_trials, np.float64)
     ev = np.zeros(len(ids), np.float64) if want_event_net else None
     ec = np.zeros(len(ids), np.float64) if want_event_cum else None
+    om = np.zeros(n_trials, np.float64) if want_occ_max else None
     rc = lib.oracle_run_layer(_ptr(ids), _ptr(off), n_trials, events_per_trial, catalog_size, layer.n_elts,
                               _ptr(eids), _ptr(elos), _ptr(sizes), _ptr(ret), _ptr(lim),
                               layer.occ_ret, layer.occ_lim, layer.agg_ret, layer.agg_lim, int(n_threads),
-                              _ptr(ylt), _ptr(occ), _ptr(gross), _ptr(ec), _ptr(ev))
+                              _ptr(ylt), _ptr(occ), _ptr(gross), _ptr(ec), _ptr(ev), _ptr(om))
     if rc != 0:
         raise OracleError(f"oracle_run_layer failed with status {rc}")
     out = {"ylt": ylt, "occ_sum": occ, "gross": gross}
@@ -103,6 +105,8 @@ def run_layer(ids: np.ndarray, offsets: Optional[np.ndarray], n_trials: int, eve
         out["event_net"] = ev
     if want_event_cum:
         out["event_cum"] = ec
+    if want_occ_max:
+        out["occ_max"] = om
     return out
 
 

@@ -50,3 +50,23 @@ def exact_layer(ids, offsets, layer):
         occ.append(S)
         gross.append(G)
     return ylt, occ, gross, net
+
+
+def exact_occ_max(ids, offsets, layer):
+    """Largest occurrence loss (after the occurrence terms) of each trial, as
+    Fractions; 0 for an empty trial."""
+    tables = [dict(zip(map(int, e), map(Fraction, l))) for e, l in zip(layer.elt_ids, layer.elt_losses)]
+    ret = [Fraction(r) for r in layer.ret]
+    lim = [_F(u) for u in layer.lim]
+    R2, L2 = Fraction(layer.occ_ret), _F(layer.occ_lim)
+    out = []
+    for i in range(len(offsets) - 1):
+        M = Fraction(0)
+        for k in range(int(offsets[i]), int(offsets[i + 1])):
+            E = int(ids[k])
+            e = Fraction(0)
+            for j, t in enumerate(tables):
+                e += _clamp(t.get(E, Fraction(0)), ret[j], lim[j])
+            M = max(M, _clamp(e, R2, L2))
+        out.append(M)
+    return out

@@ -25,7 +25,8 @@ MUTANTS = {
     "ft1_swapped": [("e += clamp_excess(l, ret[j], lim[j]);", "e += clamp_excess(l, lim[j], ret[j]);")],
     "ft2_dropped": [("double o = clamp_excess(e, occ_ret, occ_lim);", "double o = e;")],
     "ft3_per_event": [("S += o;", "S += clamp_excess(o, agg_ret, agg_lim);")],
-    "event_loss_not_reset": [("double S = 0.0, G = 0.0, A_prev = 0.0;", "double S = 0.0, G = 0.0, A_prev = 0.0, ec = 0.0;"),
+    "event_loss_not_reset": [("double S = 0.0, G = 0.0, A_prev = 0.0, M = 0.0;",
+                              "double S = 0.0, G = 0.0, A_prev = 0.0, M = 0.0, ec = 0.0;"),
                              ("double e = 0.0;", "double e = ec;"),
                              ("double o = clamp_excess(e, occ_ret, occ_lim);",
                               "double o = clamp_excess(e, occ_ret, occ_lim); ec = e;")],
@@ -38,6 +39,8 @@ MUTANTS = {
     "agg_retention_dropped": [("ylt[i] = clamp_excess(S, agg_ret, agg_lim);", "ylt[i] = clamp_excess(S, 0.0, agg_lim);")],
     "elt_order_offset": [("table[(size_t)j * C + (size_t)e] = elt_losses[pos];",
                           "table[(size_t)j * C + (size_t)e] = elt_losses[pos > 0 ? pos - 1 : pos];")],
+    "occ_max_before_ft2": [("if (o > M) M = o;", "if (e > M) M = e;")],
+    "occ_max_last_not_largest": [("if (o > M) M = o;", "M = o;")],
 }
 
 
@@ -63,6 +66,9 @@ def _pins_hold(lib) -> bool:
     except oracle.OracleError:
         return False
     if r["ylt"].tolist() != g["ylt"] or r["occ_sum"].tolist() != g["occ_sum"]:
+        return False
+    rm = oracle.run_layer(ids, off, len(off) - 1, 0, g["catalog_size"], lay, lib=lib, want_occ_max=True)
+    if rm["occ_max"].tolist() != g["occ_max"]:
         return False
     ro = oracle.run_layer(ids, off, len(off) - 1, 0, g["catalog_size"], lay.open_terms(), lib=lib)
     if ro["ylt"].tolist() != g["open_terms_ylt"]:

@@ -12,7 +12,9 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from exact_ref import exact_layer
+from fractions import Fraction
+
+from exact_ref import exact_layer, exact_occ_max
 from oracle import oracle
 from paper_1412_4556_amd import workloads as W
 
@@ -61,6 +63,19 @@ def test_worked_example_exact():
     assert ro["ylt"].tolist() == g["open_terms_ylt"]
 
 
+def test_worked_example_occ_max():
+    """Per-trial largest occurrence loss (occurrence basis), by hand."""
+    g = json.load(open(GOLD))
+    lay = _golden_layer(g)
+    ids, off = _flatten(g["trials"])
+    r = _run(ids, off, g["catalog_size"], lay, want_occ_max=True)
+    assert r["occ_max"].tolist() == g["occ_max"]
+    q = g["occ_max_pml_tvar"]
+    pml, tvar = oracle.pml_tvar(r["occ_max"], q["return_periods"])
+    assert pml.tolist() == q["pml"]
+    assert tvar.tolist() == [float(Fraction(t)) for t in q["tvar"]]
+
+
 def test_worked_example_pml_tvar():
     g = json.load(open(GOLD))
     pml, tvar = oracle.pml_tvar(np.array(g["ylt"], np.float64), g["pml_tvar"]["return_periods"])
@@ -96,6 +111,13 @@ def test_oracle_matches_exact_rationals(case):
         assert r["gross"][i] == pytest.approx(G, rel=1e-12, abs=0)
         if integer:
             assert r["ylt"][i] == float(ey[i])
+    # largest occurrence loss per trial
+    rm = _run(ids, off, C, lay, want_occ_max=True)["occ_max"]
+    em = exact_occ_max(ids, off, lay)
+    for i in range(T):
+        assert abs(rm[i] - float(em[i])) <= (J + 3) * U64 * float(eG[i]) * 1.01
+        if integer:
+            assert rm[i] == float(em[i])
     # per-event increments: sum of increments = year loss; each within bound
     for k in range(len(ids)):
         assert abs(r["event_net"][k] - float(enet[k])) <= (len(ids) + J + 3) * U64 * max(float(sum(eG)), 1.0)
@@ -310,3 +332,33 @@ def test_oracle_rejects_bad_elts():
                           0, np.inf, 0, np.inf)
     with pytest.raises(oracle.OracleError, match="-2"):
         _run(ids, off, 5, rng_bad)
+
+
+# ----------------------------------------------------------------------------- occurrence basis
+def test_occ_max_closed_forms_and_bounds():
+    """Open terms: the largest occurrence loss of a trial is the largest total
+    loss (over the ELTs) of its events.  Counting form: 1 if the trial holds an
+    event present in some ELT, else 0.  Always 0 <= occ_max <= min(S, FT2 limit)."""
+    C = 4000
+    ids, off, lay = W.random_case(12, 400, 60.0, C, 4, 700, integer_losses=True, max_int_loss=500, terms="open",
+                                  empty_frac=0.05)
+    w, present = _presence_and_totals(lay, C)
+    r = _run(ids, off, C, lay, want_occ_max=True)
+    expect = np.array([w[ids[off[i]:off[i + 1]]].max() if off[i + 1] > off[i] else 0.0 for i in range(len(off) - 1)])
+    assert np.array_equal(r["occ_max"], expect)
+    ids, off, lay = W.random_case(13, 400, 20.0, C, 3, 300, integer_losses=True, terms="counting", empty_frac=0.1)
+    _, present = _presence_and_totals(lay, C)
+    r = _run(ids, off, C, lay, want_occ_max=True)
+    expect = np.array([float(present[ids[off[i]:off[i + 1]]].any()) for i in range(len(off) - 1)])
+    assert np.array_equal(r["occ_max"], expect)
+    ids, off, lay = W.random_case(14, 300, 80.0, C, 5, 900)
+    r = _run(ids, off, C, lay, want_occ_max=True)
+    assert np.all(r["occ_max"] >= 0.0)
+    assert np.all(r["occ_max"] <= lay.occ_lim)
+    assert np.all(r["occ_max"] <= r["occ_sum"])
+    # order of events inside a trial does not matter
+    rng = np.random.default_rng(5)
+    pid = ids.copy()
+    for i in range(len(off) - 1):
+        rng.shuffle(pid[off[i]:off[i + 1]])
+    assert np.array_equal(_run(pid, off, C, lay, want_occ_max=True)["occ_max"], r["occ_max"])
