@@ -308,6 +308,21 @@ def main():
         torch.cuda.synchronize()
         extras["per_event_net_output"] = {"kernel_ms": round(ev0.elapsed_time(ev1), 4)}
         del out
+        # occurrence basis: YLT plus the largest occurrence loss per trial
+        A.run_layer_max_occurrence(yet, lay)
+        torch.cuda.synchronize()
+        ms_occ = []
+        for _ in range(5):
+            ev0.record()
+            _, mx = A.run_layer_max_occurrence(yet, lay)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms_occ.append(ev0.elapsed_time(ev1))
+        opml, otvar = A.pml_tvar(mx, rps)
+        extras["max_occurrence_output"] = {"kernel_ms": round(sorted(ms_occ)[2], 4),
+                                           "occurrence_pml": [float(v) for v in opml],
+                                           "occurrence_tvar": [float(v) for v in otvar]}
+        del mx
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(5):

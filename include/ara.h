@@ -151,6 +151,20 @@ ara_status ara_run_layer(ara_yet yet, ara_layer layer, double *d_ylt, void *hip_
 ara_status ara_run_layer_events(ara_yet yet, ara_layer layer, double *d_ylt, double *d_event_cum,
                                 double *d_event_net, void *hip_stream);
 
+/* The trial pass with the loss on an occurrence basis as well: the largest
+ * occurrence loss of each trial (the event losses net of the occurrence
+ * terms, Section III step 3; 0 for an empty trial).  PML, TVaR and return
+ * period losses on the occurrence basis follow from it with ara_pml_tvar as
+ * they do from the YLT on the aggregate basis (Section III names these
+ * metrics and return period losses as products of the analysis).
+ *   d_ylt      binary64 [n_trials] as in ara_run_layer (required).
+ *   d_max_occ  binary64 [n_trials], caller-owned device memory (required).
+ * With ARA_FP64 layers d_max_occ holds exactly the largest of the binary64
+ * occurrence losses; with ARA_FP32C, the largest binary32 one.  The YLT is
+ * bitwise the one of ara_run_layer.  Asynchronous on hip_stream. */
+ara_status ara_run_layer_max_occurrence(ara_yet yet, ara_layer layer, double *d_ylt, double *d_max_occ,
+                                        void *hip_stream);
+
 /* Several layers over one YET in one pass (Algorithm 1's loop over the
  * layers of a program, with the YET read once for all of them).
  *

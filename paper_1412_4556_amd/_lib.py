@@ -36,6 +36,7 @@ SIGNATURES = {
     "ara_create_layer": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _D, _D, _D, _D, _I32, _I32, _P]),
     "ara_run_layer": (_I32, [_P, _P, _P, _P]),
     "ara_run_layer_events": (_I32, [_P, _P, _P, _P, _P, _P]),
+    "ara_run_layer_max_occurrence": (_I32, [_P, _P, _P, _P, _P]),
     "ara_run_layers": (_I32, [_P, _P, _P, _I32, _P]),
     "ara_create_batch": (_I32, [_P, _P, _I32, _P]),
     "ara_run_batch": (_I32, [_P, _P, _P]),

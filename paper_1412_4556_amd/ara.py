@@ -197,6 +197,17 @@ def run_layer_events(yet: Yet, layer: Layer, want_cum: bool = True, want_net: bo
     return ylt, cum, net
 
 
+def run_layer_max_occurrence(yet: Yet, layer: Layer, stream=None):
+    """(ylt, max_occ): the YLT and, per trial, the largest occurrence loss
+    (float64 [n_trials] each); asynchronous on the stream."""
+    dev = yet.event_ids.device
+    ylt = torch.empty(yet.n_trials, dtype=torch.float64, device=dev)
+    mx = torch.empty(yet.n_trials, dtype=torch.float64, device=dev)
+    L.check(L.lib().ara_run_layer_max_occurrence(yet.handle, layer.handle, ctypes.c_void_p(ylt.data_ptr()),
+                                                 ctypes.c_void_p(mx.data_ptr()), ctypes.c_void_p(_stream(stream))))
+    return ylt, mx
+
+
 class Batch:
     """Several fused layers prepared for one pass over the YET."""
 

@@ -476,7 +476,21 @@ ara_status ara_run_layer(ara_yet yet, ara_layer layer, double *d_ylt, void *hip_
         hipError_t we = hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), layer->ready, 0);
         if (we != hipSuccess) return hip_fail(we, "waiting for the layer build");
     }
-    hipError_t e = ara::launch_trial_pass(yet->v, layer->h, d_ylt, static_cast<hipStream_t>(hip_stream));
+    hipError_t e = ara::launch_trial_pass(yet->v, layer->h, d_ylt, nullptr, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "trial pass launch");
+    return ARA_OK;
+}
+
+ara_status ara_run_layer_max_occurrence(ara_yet yet, ara_layer layer, double *d_ylt, double *d_max_occ,
+                                        void *hip_stream) {
+    if (!yet || !layer) return fail(ARA_ERR_INVALID_ARG, "NULL handle");
+    if (layer->h.catalog != yet->catalog) return fail(ARA_ERR_INVALID_ARG, "layer built for another catalogue");
+    if (yet->v.n_trials > 0 && (!d_ylt || !d_max_occ)) return fail(ARA_ERR_INVALID_ARG, "d_ylt or d_max_occ is NULL");
+    if (layer->ready) {
+        hipError_t we = hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), layer->ready, 0);
+        if (we != hipSuccess) return hip_fail(we, "waiting for the layer build");
+    }
+    hipError_t e = ara::launch_trial_pass(yet->v, layer->h, d_ylt, d_max_occ, static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "trial pass launch");
     return ARA_OK;
 }

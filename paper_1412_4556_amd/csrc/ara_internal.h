@@ -98,7 +98,8 @@ hipStream_t internal_stream();
 // present_ids[n_present]), then the LDS filter bits.
 hipError_t launch_fuse(LayerHost &L, const void *d_rows, const int32_t *d_present, int64_t n_present, hipStream_t s);
 hipError_t launch_validate_yet(const YetView &y, int32_t catalog, int32_t *d_flags, hipStream_t s);
-hipError_t launch_trial_pass(const YetView &y, const LayerHost &L, double *d_ylt, hipStream_t s);
+// d_omax (optional, [n_trials]): the largest occurrence loss of each trial.
+hipError_t launch_trial_pass(const YetView &y, const LayerHost &L, double *d_ylt, double *d_omax, hipStream_t s);
 hipError_t launch_trial_pass_events(const YetView &y, const LayerHost &L, double *d_ylt, double *d_cum,
                                     double *d_net, hipStream_t s);
 

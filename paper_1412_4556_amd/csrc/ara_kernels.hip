@@ -155,6 +155,17 @@ __device__ __forceinline__ Acc<T> wave_allreduce(Acc<T> a) {
     return a;
 }
 
+// Largest value over the wave (exact; every lane ends with it).
+template <typename T>
+__device__ __forceinline__ T wave_max(T x) {
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) {
+        const T o = __shfl_xor(x, m);
+        x = o > x ? o : x;
+    }
+    return x;
+}
+
 // --------------------------------------------------------------------------------------------
 // occurrence loss of one event (Section III steps 1-3) for each layout
 template <typename T, int LAYOUT>
@@ -265,22 +276,33 @@ __device__ __forceinline__ int64_t chunk_start(const YetView &y, int64_t b) { re
 // --------------------------------------------------------------------------------------------
 // kernels
 template <typename T, int LAYOUT>
-__global__ __launch_bounds__(256) void k_trial_pass(YetView y, TablesView tb, Terms<T> t, double *__restrict__ ylt) {
+// omax (optional): the largest occurrence loss of each trial.
+__global__ __launch_bounds__(256) void k_trial_pass(YetView y, TablesView tb, Terms<T> t, double *__restrict__ ylt,
+                                                    double *__restrict__ omax) {
     const int lane = lane_id();
     const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t trial = wave; trial < y.n_trials; trial += n_waves) {
         const TrialRange r = trial_range(y, trial);
         Acc<T> acc = Acc<T>::zero();
+        T m = T(0);
         for (int64_t p = chunk_start(y, r.b) + 4 * lane; p < r.e; p += 4 * kWave) {
             int32_t id[4];
             load4(y, p, r, id);
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                if (id[v] >= 0) acc.add(Lookup<T, LAYOUT>::occ(id[v], tb, t));
+                if (id[v] >= 0) {
+                    const T o = Lookup<T, LAYOUT>::occ(id[v], tb, t);
+                    acc.add(o);
+                    m = o > m ? o : m;
+                }
         }
         const double S = wave_allreduce(acc).value();
         if (lane == 0) ylt[trial] = clamp_excess(S, t.agg_ret, t.agg_lim);
+        if (omax) {
+            m = wave_max(m);
+            if (lane == 0) omax[trial] = (double)m;
+        }
     }
 }
 
@@ -463,6 +485,16 @@ __device__ __forceinline__ void accumulate_group(const T (&o)[G][4], Acc<T> &acc
         }
 }
 
+// Largest of a group's occurrence losses (skipped events hold exact zeros,
+// and every occurrence loss is >= 0).
+template <typename T, int G = kGroup>
+__device__ __forceinline__ void max_group(const T (&o)[G][4], T &m) {
+#pragma unroll
+    for (int c = 0; c < G; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) m = o[c][v] > m ? o[c][v] : m;
+}
+
 // Trial bounds; fixed-length trials (off == nullptr) need not be FIXED: their
 // length may not be a multiple of 4 or the IDs may be unaligned.
 template <bool FIXED>
@@ -471,11 +503,12 @@ __device__ __forceinline__ TrialRange fused_range(const YetView &y, const int64_
     return TrialRange{off[i], off[i + 1]};
 }
 
-template <typename T, bool FIXED, bool ALIGNED, bool HASH, int G>
+// OMAX: also the largest occurrence loss of each trial, into omax.
+template <typename T, bool FIXED, bool ALIGNED, bool HASH, int G, bool OMAX>
 __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int64_t *__restrict__ off, FusedFilter f,
                                                            int32_t zero_slot, const T *__restrict__ occ,
                                                            double agg_ret, double agg_lim,
-                                                           double *__restrict__ ylt) {
+                                                           double *__restrict__ ylt, double *__restrict__ omax) {
     extern __shared__ uint32_t sfilt[];
     load_filters(f, sfilt);
     const int lane = lane_id();
@@ -503,14 +536,21 @@ __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int6
         const uint32_t nxt_valid = load_group<FIXED, ALIGNED, G>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
         Acc<T> acc = Acc<T>::zero();
         accumulate_group(o, acc);
+        T m = T(0);
+        if (OMAX) max_group(o, m);
         for (int64_t base = chunk_start(y, r.b) + kSpan; base < r.e; base += kSpan) {
             IdGroupT<G> more;
             const uint32_t mv = load_group<FIXED, ALIGNED, G>(y, r, base, lane, last_granule, more);
             gather_group<T, HASH, G>(more, mv, sfilt, f, zero_slot, occ, o);
             accumulate_group(o, acc);
+            if (OMAX) max_group(o, m);
         }
         const double S = wave_allreduce(acc).value();
         if (lane == 0) ylt[trial] = clamp_excess(S, agg_ret, agg_lim);
+        if (OMAX) {
+            m = wave_max(m);
+            if (lane == 0) omax[trial] = (double)m;
+        }
         trial = next;
         r = rn;
         cur = nxt;
@@ -908,7 +948,7 @@ int grid_for_trials(int64_t n_trials, int waves_per_block, int blocks_per_cu) {
 
 template <typename T>
 hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t, double *d_ylt, double *d_cum,
-                         double *d_net, bool events, hipStream_t s) {
+                         double *d_net, double *d_omax, bool events, hipStream_t s) {
     if (y.n_trials == 0) return hipSuccess;
     const int grid = grid_for_trials(y.n_trials, 4, 8);
     const dim3 blk(256);
@@ -923,13 +963,20 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
         // second group (the per-event pass has no registers to spare for it)
         const bool wide = !events && !fixed && y.aligned16 && y.n_trials > 0 && y.n_events / y.n_trials > 768;
         const int variant = wide ? (hash ? 7 : 6) : (fixed ? 0 : (y.aligned16 ? 1 : 2)) + (hash ? 3 : 0);
-        using PassK = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const T *, double, double, double *);
+        using PassK = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const T *, double, double, double *,
+                               double *);
         using EventsK = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const T *, double, double, double *,
                                  double *, double *);
-        const PassK pk[8] = {&k_trial_pass_fused<T, true, true, false, 4>,   &k_trial_pass_fused<T, false, true, false, 4>,
-                             &k_trial_pass_fused<T, false, false, false, 4>, &k_trial_pass_fused<T, true, true, true, 4>,
-                             &k_trial_pass_fused<T, false, true, true, 4>,   &k_trial_pass_fused<T, false, false, true, 4>,
-                             &k_trial_pass_fused<T, false, true, false, 5>,  &k_trial_pass_fused<T, false, true, true, 5>};
+        const PassK pk[16] = {
+            &k_trial_pass_fused<T, true, true, false, 4, false>,  &k_trial_pass_fused<T, false, true, false, 4, false>,
+            &k_trial_pass_fused<T, false, false, false, 4, false>, &k_trial_pass_fused<T, true, true, true, 4, false>,
+            &k_trial_pass_fused<T, false, true, true, 4, false>,  &k_trial_pass_fused<T, false, false, true, 4, false>,
+            &k_trial_pass_fused<T, false, true, false, 5, false>, &k_trial_pass_fused<T, false, true, true, 5, false>,
+            &k_trial_pass_fused<T, true, true, false, 4, true>,   &k_trial_pass_fused<T, false, true, false, 4, true>,
+            &k_trial_pass_fused<T, false, false, false, 4, true>, &k_trial_pass_fused<T, true, true, true, 4, true>,
+            &k_trial_pass_fused<T, false, true, true, 4, true>,   &k_trial_pass_fused<T, false, false, true, 4, true>,
+            &k_trial_pass_fused<T, false, true, false, 5, true>,  &k_trial_pass_fused<T, false, true, true, 5, true>};
+        const int pv = variant + (d_omax ? 8 : 0);
         const EventsK ek[8] = {&k_trial_pass_events_fused<T, true, true, false, 4>,
                                &k_trial_pass_events_fused<T, false, true, false, 4>,
                                &k_trial_pass_events_fused<T, false, false, false, 4>,
@@ -938,9 +985,9 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
                                &k_trial_pass_events_fused<T, false, false, true, 4>,
                                nullptr,
                                nullptr};
-        const void *kern = events ? reinterpret_cast<const void *>(ek[variant]) : reinterpret_cast<const void *>(pk[variant]);
-        static bool attr_set[2][2][8] = {};
-        bool &done = attr_set[sizeof(T) == 8 ? 0 : 1][events ? 1 : 0][variant];
+        const void *kern = events ? reinterpret_cast<const void *>(ek[variant]) : reinterpret_cast<const void *>(pk[pv]);
+        static bool attr_set[2][2][16] = {};
+        bool &done = attr_set[sizeof(T) == 8 ? 0 : 1][events ? 1 : 0][events ? variant : pv];
         if (!done) {
             hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsBytes);
             if (e != hipSuccess) return e;
@@ -950,8 +997,8 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
         const int fgrid = grid_for_trials(y.n_trials, 16, per_cu);
         const T *occ = static_cast<const T *>(L.tab.occ);
         if (!events) {
-            hipLaunchKernelGGL(pk[variant], dim3(fgrid), dim3(1024), lds, s, y, y.offsets, f, L.catalog, occ, t.agg_ret,
-                               t.agg_lim, d_ylt);
+            hipLaunchKernelGGL(pk[pv], dim3(fgrid), dim3(1024), lds, s, y, y.offsets, f, L.catalog, occ, t.agg_ret,
+                               t.agg_lim, d_ylt, d_omax);
         } else {
             hipLaunchKernelGGL(ek[variant], dim3(fgrid), dim3(1024), lds, s, y, y.offsets, f, L.catalog, occ, t.agg_ret,
                                t.agg_lim, d_ylt, d_cum, d_net);
@@ -960,10 +1007,10 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
     }
     if (!events) {
         switch (L.layout) {
-            case kDirect: hipLaunchKernelGGL((k_trial_pass<T, kDirect>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt); break;
-            case kSparse: hipLaunchKernelGGL((k_trial_pass<T, kSparse>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt); break;
-            case kFused: hipLaunchKernelGGL((k_trial_pass<T, kFused>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt); break;
-            default: hipLaunchKernelGGL((k_trial_pass<T, kCompact>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt); break;
+            case kDirect: hipLaunchKernelGGL((k_trial_pass<T, kDirect>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt, d_omax); break;
+            case kSparse: hipLaunchKernelGGL((k_trial_pass<T, kSparse>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt, d_omax); break;
+            case kFused: hipLaunchKernelGGL((k_trial_pass<T, kFused>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt, d_omax); break;
+            default: hipLaunchKernelGGL((k_trial_pass<T, kCompact>), dim3(grid), blk, 0, s, y, L.tab, t, d_ylt, d_omax); break;
         }
     } else {
         switch (L.layout) {
@@ -1032,15 +1079,15 @@ hipError_t launch_validate_yet(const YetView &y, int32_t catalog, int32_t *d_fla
     return hipGetLastError();
 }
 
-hipError_t launch_trial_pass(const YetView &y, const LayerHost &L, double *d_ylt, hipStream_t s) {
-    if (L.precision == ARA_FP32C) return launch_pass_t<float>(y, L, L.t32, d_ylt, nullptr, nullptr, false, s);
-    return launch_pass_t<double>(y, L, L.t64, d_ylt, nullptr, nullptr, false, s);
+hipError_t launch_trial_pass(const YetView &y, const LayerHost &L, double *d_ylt, double *d_omax, hipStream_t s) {
+    if (L.precision == ARA_FP32C) return launch_pass_t<float>(y, L, L.t32, d_ylt, nullptr, nullptr, d_omax, false, s);
+    return launch_pass_t<double>(y, L, L.t64, d_ylt, nullptr, nullptr, d_omax, false, s);
 }
 
 hipError_t launch_trial_pass_events(const YetView &y, const LayerHost &L, double *d_ylt, double *d_cum,
                                     double *d_net, hipStream_t s) {
-    if (L.precision == ARA_FP32C) return launch_pass_t<float>(y, L, L.t32, d_ylt, d_cum, d_net, true, s);
-    return launch_pass_t<double>(y, L, L.t64, d_ylt, d_cum, d_net, true, s);
+    if (L.precision == ARA_FP32C) return launch_pass_t<float>(y, L, L.t32, d_ylt, d_cum, d_net, nullptr, true, s);
+    return launch_pass_t<double>(y, L, L.t64, d_ylt, d_cum, d_net, nullptr, true, s);
 }
 
 namespace {

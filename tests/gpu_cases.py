@@ -9,7 +9,7 @@ from paper_1412_4556_amd import ara as A
 TOL = {"fp64": 1e-12, "fp32c": 1e-6}
 
 
-def gpu_layer_run(ids, off, T, C, K, spec, prec, layout, events=False, ids_misalign=False):
+def gpu_layer_run(ids, off, T, C, K, spec, prec, layout, events=False, ids_misalign=False, max_occ=False):
     """YLT (and per-event outputs) of the HIP path, copied to the host."""
     if ids_misalign:
         # place the IDs one element into a bigger buffer: not 16-byte aligned
@@ -26,6 +26,10 @@ def gpu_layer_run(ids, off, T, C, K, spec, prec, layout, events=False, ids_misal
         y, cum, net = A.run_layer_events(yet, lay)
         torch.cuda.synchronize()
         out = (y.cpu().numpy(), cum.cpu().numpy(), net.cpu().numpy())
+    elif max_occ:
+        y, mx = A.run_layer_max_occurrence(yet, lay)
+        torch.cuda.synchronize()
+        out = (y.cpu().numpy(), mx.cpu().numpy())
     else:
         y = A.run_layer(yet, lay)
         torch.cuda.synchronize()

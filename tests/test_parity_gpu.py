@@ -48,6 +48,18 @@ def test_worked_example(prec, layout):
     assert y2.tolist() == g["ylt"]
     assert [cum[off[i]:off[i + 1]].tolist() for i in range(T)] == g["event_cum"]
     assert [net[off[i]:off[i + 1]].tolist() for i in range(T)] == g["event_net"]
+    y3, mx = gpu_layer_run(ids, off, T, g["catalog_size"], 0, spec, prec, layout, max_occ=True)
+    assert y3.tolist() == g["ylt"]
+    assert mx.tolist() == g["occ_max"]
+
+
+def test_worked_example_occurrence_basis_pml_tvar():
+    from fractions import Fraction
+    g, *_ = _golden()
+    q = g["occ_max_pml_tvar"]
+    pml, tvar = A.pml_tvar(torch.tensor(g["occ_max"], dtype=torch.float64, device="cuda"), q["return_periods"])
+    assert pml.tolist() == q["pml"]
+    assert np.allclose(tvar, [float(Fraction(t)) for t in q["tvar"]], rtol=1e-15, atol=0)
 
 
 def test_worked_example_pml_tvar():
@@ -143,11 +155,21 @@ EDGE = [
 def test_edge_cases(name, kw, misalign, prec):
     ids, off, spec = W.random_case(**kw)
     T, C = kw["n_trials"], kw["catalog"]
-    ref = oracle_run(ids, off, T, C, 0, spec, want_event_cum=True, want_event_net=True)
+    ref = oracle_run(ids, off, T, C, 0, spec, want_event_cum=True, want_event_net=True, want_occ_max=True)
     ys = [gpu_layer_run(ids, off, T, C, 0, spec, prec, lay, ids_misalign=misalign) for lay in LAYOUTS]
     assert_close_to_oracle(ys[0], ref, prec)
     for other in ys[1:]:
         assert np.array_equal(ys[0], other)
+    # occurrence basis: the largest occurrence loss per trial, every layout;
+    # with binary64 layers it is exactly the oracle's (a maximum of bitwise
+    # equal occurrence losses)
+    for lay in LAYOUTS:
+        y, mx = gpu_layer_run(ids, off, T, C, 0, spec, prec, lay, ids_misalign=misalign, max_occ=True)
+        assert np.array_equal(y, ys[0])
+        if prec == "fp64":
+            assert np.array_equal(mx, ref["occ_max"]), lay
+        else:
+            assert np.all(np.abs(mx - ref["occ_max"]) <= TOL[prec] * ref["gross"]), lay
     y, cum, net = gpu_layer_run(ids, off, T, C, 0, spec, prec, "fused", events=True, ids_misalign=misalign)
     assert_close_to_oracle(y, ref, prec)
     # the fused per-event pass is bitwise the generic one (compact layout)

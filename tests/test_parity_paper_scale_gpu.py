@@ -77,3 +77,30 @@ def test_paper_scale_per_event_outputs(paper, prec):
     assert np.allclose(net_s.sum(axis=1), y.cpu().numpy()[sample], rtol=0, atol=1e-9 * ref["gross"].max())
     del cum, net
     lay.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_paper_scale_max_occurrence(paper, prec):
+    """Occurrence basis at full size (fused layout): the largest occurrence
+    loss of the sampled trials, exact in binary64; PML/TVaR of the full array
+    agree with the oracle's selection routine applied to it."""
+    wl, yet, spec, sample, ref = paper
+    from paper_1412_4556_amd import workloads as W2
+    sub_ids, sub_off = W2.yet_subset(wl.yet, sample)
+    ref_m = oracle_run(sub_ids, sub_off, len(sample), wl.yet.catalog_size, 0, spec, want_occ_max=True)
+    lay = A.Layer(yet, spec, prec, "fused")
+    y, mx = A.run_layer_max_occurrence(yet, lay)
+    y_plain = A.run_layer(yet, lay)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y_plain)
+    m = mx.cpu().numpy()
+    if prec == "fp64":
+        assert np.array_equal(m[sample], ref_m["occ_max"])
+    else:
+        assert np.all(np.abs(m[sample] - ref_m["occ_max"]) <= TOL[prec] * ref_m["gross"])
+    assert np.all(m <= spec.occ_lim) and np.all(m >= 0)
+    gp, gt = A.pml_tvar(mx, wl.return_periods)
+    op, ot = oracle.pml_tvar(m, wl.return_periods)
+    assert np.array_equal(gp, op)
+    assert np.allclose(gt, ot, rtol=1e-12, atol=0)
+    lay.close()
