@@ -44,9 +44,13 @@ __device__ __forceinline__ double key_value(unsigned long long key) {
     return __longlong_as_double((long long)u);
 }
 
+struct TailSizes {
+    long long k[kMaxRp];
+};
+
 // selection s = y * n_rp + r
-__global__ void k_sel_init(SelState *st, const long long *k, int n_rp, int n_sel, unsigned *hist, int *nan_flag) {
-    for (int s = threadIdx.x; s < n_sel; s += blockDim.x) st[s] = SelState{0ULL, 0ULL, k[s % n_rp], k[s % n_rp]};
+__global__ void k_sel_init(SelState *st, TailSizes k, int n_rp, int n_sel, unsigned *hist, int *nan_flag) {
+    for (int s = threadIdx.x; s < n_sel; s += blockDim.x) st[s] = SelState{0ULL, 0ULL, k.k[s % n_rp], k.k[s % n_rp]};
     for (int i = threadIdx.x; i < n_sel * 256; i += blockDim.x) hist[i] = 0u;
     if (threadIdx.x == 0) *nan_flag = 0;
 }
@@ -173,11 +177,13 @@ __global__ __launch_bounds__(kSumBlocks) void k_tail_finish(const SelState *st, 
     }
 }
 
-// Library-owned scratch per device; ara_pml_tvar is synchronous and holds
-// the device's lock for the duration of a call.
+// Library-owned scratch per device (device memory and a pinned host buffer
+// for the results); ara_pml_tvar is synchronous and holds the device's lock
+// for the duration of a call.
 struct Scratch {
     std::mutex mu;
     void *d = nullptr;
+    void *h = nullptr;
 };
 
 Scratch &scratch_for(int dev) {
@@ -195,15 +201,13 @@ hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n
     if (e != hipSuccess) return e;
     Scratch &sc = scratch_for(dev);
     std::lock_guard<std::mutex> g(sc.mu);
-    // layout: state | k | hist | psum | pcnt | out | nan
-    const size_t off_state = 0;
-    const size_t off_k = off_state + sizeof(SelState) * kMaxSel;
-    const size_t off_hist = off_k + sizeof(long long) * kMaxRp;
+    // layout: result (nan flag, then PML/TVaR pairs) | state | hist | psum | pcnt
+    const size_t res_bytes = 16 + sizeof(double) * 2 * kMaxSel;
+    const size_t off_state = res_bytes;
+    const size_t off_hist = off_state + sizeof(SelState) * kMaxSel;
     const size_t off_psum = off_hist + sizeof(unsigned) * 256 * kMaxSel;
     const size_t off_pcnt = off_psum + sizeof(double) * kSumBlocks * kMaxSel;
-    const size_t off_out = off_pcnt + sizeof(unsigned long long) * kSumBlocks * kMaxSel;
-    const size_t off_nan = off_out + sizeof(double) * 2 * kMaxSel;
-    const size_t total = off_nan + 256;
+    const size_t total = off_pcnt + sizeof(unsigned long long) * kSumBlocks * kMaxSel;
     if (!sc.d) {
         e = hipMalloc(&sc.d, total);
         if (e != hipSuccess) {
@@ -211,22 +215,28 @@ hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n
             return e;
         }
     }
+    if (!sc.h) {
+        e = hipHostMalloc(&sc.h, res_bytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            sc.h = nullptr;
+            return e;
+        }
+    }
     char *base = static_cast<char *>(sc.d);
+    int *nan_flag = reinterpret_cast<int *>(base);
+    double *out = reinterpret_cast<double *>(base + 16);
     SelState *st = reinterpret_cast<SelState *>(base + off_state);
-    long long *dk = reinterpret_cast<long long *>(base + off_k);
     unsigned *hist = reinterpret_cast<unsigned *>(base + off_hist);
     double *psum = reinterpret_cast<double *>(base + off_psum);
     unsigned long long *pcnt = reinterpret_cast<unsigned long long *>(base + off_pcnt);
-    double *out = reinterpret_cast<double *>(base + off_out);
-    int *nan_flag = reinterpret_cast<int *>(base + off_nan);
     const int n_sel = n_ylt * n_rp;
 
     YltPtrs yp{};
     for (int i = 0; i < n_ylt; ++i) yp.p[i] = d_ylts[i];
-    long long hk[kMaxRp];
-    for (int r = 0; r < n_rp; ++r) hk[r] = (long long)h_k[r];
-    if ((e = hipMemcpyAsync(dk, hk, sizeof(long long) * n_rp, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(1024), 0, s, st, dk, n_rp, n_sel, hist, nan_flag);
+    // tail sizes travel as a kernel argument (no host-to-device copy)
+    TailSizes tk{};
+    for (int r = 0; r < n_rp; ++r) tk.k[r] = (long long)h_k[r];
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(1024), 0, s, st, tk, n_rp, n_sel, hist, nan_flag);
     long long gx = (n + kThreads - 1) / kThreads;
     const long long cap = n_ylt > 8 ? 64 : 512;
     if (gx > cap) gx = cap;
@@ -239,14 +249,14 @@ hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n
     hipLaunchKernelGGL(k_tail_sum, dim3(kSumBlocks, n_ylt), dim3(kThreads), 0, s, yp, (long long)n, st, n_rp, psum, pcnt);
     hipLaunchKernelGGL(k_tail_finish, dim3(n_sel), dim3(kSumBlocks), 0, s, st, psum, pcnt, out);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    std::vector<double> hout(2 * (size_t)n_sel);
-    int hn = 0;
-    if ((e = hipMemcpyAsync(hout.data(), out, sizeof(double) * 2 * n_sel, hipMemcpyDeviceToHost, s)) != hipSuccess)
-        return e;
-    if ((e = hipMemcpyAsync(&hn, nan_flag, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    // one copy of the flag and the results into pinned memory
+    const size_t got = 16 + sizeof(double) * 2 * (size_t)n_sel;
+    if ((e = hipMemcpyAsync(sc.h, sc.d, got, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    for (int i = 0; i < 2 * n_sel; ++i) h_out[i] = hout[i];
-    *h_nan = hn;
+    const char *hb = static_cast<const char *>(sc.h);
+    *h_nan = *reinterpret_cast<const int *>(hb);
+    const double *ho = reinterpret_cast<const double *>(hb + 16);
+    for (int i = 0; i < 2 * n_sel; ++i) h_out[i] = ho[i];
     return hipSuccess;
 }
 
