@@ -312,3 +312,13 @@ def test_create_errors():
     lay = A.Layer(yet, one([0, 5], [3.0, 4.0]))
     y = A.run_layer(yet, lay).cpu().numpy()
     assert y.tolist() == [3.0, 4.0]
+    # the occurrence-basis entry point needs both output arrays
+    import ctypes
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    rc = L.lib().ara_run_layer_max_occurrence(yet.handle, lay.handle, ctypes.c_void_p(out.data_ptr()), None, None)
+    assert L.ERRORS.get(rc) == "ARA_ERR_INVALID_ARG"
+    rc = L.lib().ara_run_layer_max_occurrence(None, lay.handle, ctypes.c_void_p(out.data_ptr()),
+                                              ctypes.c_void_p(out.data_ptr()), None)
+    assert L.ERRORS.get(rc) == "ARA_ERR_INVALID_ARG"
+    y2, mx = A.run_layer_max_occurrence(yet, lay)
+    assert y2.cpu().tolist() == [3.0, 4.0] and mx.cpu().tolist() == [3.0, 4.0]
