@@ -717,7 +717,9 @@ ara_status ara_batch_rebuild(ara_batch b, const ara_layer *layers, int32_t n_lay
     if (e == hipSuccess) e = hipMemcpyAsync(h_ctr, b->d_ctr, sizeof(h_ctr), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "counting the batch records");
-    const unsigned long long n_ovf = h_ctr[0];
+    // at least one overflow slot: the pass prefetches overflow entries of
+    // every event at clamped indices, slot 0 for events without any
+    const unsigned long long n_ovf = h_ctr[0] > 0 ? h_ctr[0] : 1;
     if (n_ovf >= (1ULL << 32)) return fail(ARA_ERR_UNSUPPORTED, "too many overflow entries for one batch");
     if (n_ovf > b->ovf_cap) {
         // grows only; freeing waits for the device

@@ -715,9 +715,46 @@ __device__ __forceinline__ void acc_add(Acc<T> *acc, uint32_t l, int lane, T v) 
     acc[l * kAccStride + lane] = a;
 }
 
+// The overflow entries of the four events a lane holds in one chunk: the
+// first kOvPre of each are requested together (at clamped indices, slot 0
+// for events without overflow), so a chunk waits for one round trip rather
+// than one per entry.
+constexpr int kOvPre = 4;
+
 template <typename T>
-__device__ __forceinline__ void add_record(const Record<T> &r, bool valid, Acc<T> *acc, int lane,
-                                           const BatchTables &b) {
+struct OvHeads {
+    uint32_t pos[4];
+    int cnt[4];
+    int32_t lid[4][kOvPre];
+    T val[4][kOvPre];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_ov_heads(const Record<T> (&rr)[4], uint32_t valid4, const BatchTables &b,
+                                              OvHeads<T> &h) {
+    constexpr int KV = RecFormat<T>::kVals;
+    const T *ov = static_cast<const T *>(b.ovf_val);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const bool ovf = ((valid4 >> v) & 1u) && rr[v].lid[7] == kOverflowMark;
+        uint32_t pos;
+        __builtin_memcpy(&pos, &rr[v].val[KV - 1], sizeof(pos));
+        h.pos[v] = ovf ? pos : 0u;
+        h.cnt[v] = ovf ? (int)rr[v].lid[KV - 1] : 0;
+#pragma unroll
+        for (int j = 0; j < kOvPre; ++j) {
+            const uint32_t i = h.pos[v] + (j < h.cnt[v] ? (uint32_t)j : 0u);
+            h.lid[v][j] = b.ovf_lid[i];
+            h.val[v][j] = ov[i];
+        }
+    }
+}
+
+// Adds one event's entries: the inline ones, then its overflow entries in
+// order (the prefetched heads, then any further ones).
+template <typename T>
+__device__ __forceinline__ void add_event(const Record<T> &r, bool valid, const OvHeads<T> &h, int v, Acc<T> *acc,
+                                          int lane, const BatchTables &b) {
     constexpr int KV = RecFormat<T>::kVals;
     if (!valid) return;
     const bool ovf = r.lid[7] == kOverflowMark;
@@ -725,12 +762,23 @@ __device__ __forceinline__ void add_record(const Record<T> &r, bool valid, Acc<T
 #pragma unroll
     for (int k = 0; k < KV; ++k)
         if (k < n_in && r.lid[k] != kNoLayer) acc_add(acc, r.lid[k], lane, r.val[k]);
-    if (ovf) {
-        uint32_t pos;
-        __builtin_memcpy(&pos, &r.val[KV - 1], sizeof(pos));
-        const int cnt = r.lid[KV - 1];
-        const T *ov = static_cast<const T *>(b.ovf_val);
-        for (int i = 0; i < cnt; ++i) acc_add(acc, b.ovf_lid[pos + i], lane, ov[pos + i]);
+#pragma unroll
+    for (int j = 0; j < kOvPre; ++j)
+        if (j < h.cnt[v]) acc_add(acc, (uint32_t)h.lid[v][j], lane, h.val[v][j]);
+    // further entries, kOvPre at a time (requested together, added in order)
+    const T *ov = static_cast<const T *>(b.ovf_val);
+    for (int i0 = kOvPre; i0 < h.cnt[v]; i0 += kOvPre) {
+        int32_t lid[kOvPre];
+        T val[kOvPre];
+#pragma unroll
+        for (int j = 0; j < kOvPre; ++j) {
+            const uint32_t i = h.pos[v] + (uint32_t)(i0 + j < h.cnt[v] ? i0 + j : i0);
+            lid[j] = b.ovf_lid[i];
+            val[j] = ov[i];
+        }
+#pragma unroll
+        for (int j = 0; j < kOvPre; ++j)
+            if (i0 + j < h.cnt[v]) acc_add(acc, (uint32_t)lid[j], lane, val[j]);
     }
 }
 
@@ -786,13 +834,15 @@ __global__ __launch_bounds__(512) void k_trial_pass_batch(YetView y, const int64
         while (true) {
 #pragma unroll
             for (int c = 0; c < kGroup; ++c) {
+                OvHeads<T> oh;
+                load_ov_heads(rr[c & 1], (valid >> (4 * c)) & 0xfu, b, oh);
                 if (c + 1 < kGroup) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) rr[(c + 1) & 1][v] = rec[g.id[c + 1][v]];
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    add_record(rr[c & 1][v], ((valid >> (4 * c + v)) & 1u) != 0u, acc, lane, b);
+                    add_event(rr[c & 1][v], ((valid >> (4 * c + v)) & 1u) != 0u, oh, v, acc, lane, b);
             }
             base += kSpan;
             if (base >= r.e) break;
