@@ -202,7 +202,11 @@ void ara_destroy_batch(ara_batch batch);
 ara_status ara_run_layers(ara_yet yet, const ara_layer *layers, double *const *d_ylts, int32_t n_layers,
                           void *hip_stream);
 
-/* PML and TVaR of a YLT for n_rp return periods (years, > 0).
+/* PML and TVaR of a YLT for n_rp return periods (years, > 0).  The paper
+ * names Probable Maximum Loss and Tail Value-at-Risk as the risk metrics
+ * derived from the YLT (Sections I and III) without defining them; here, on
+ * the YLT's (aggregate) basis or on any per-trial loss array such as the
+ * largest occurrence losses:
  *   d_ylt              binary64 [n_trials] device memory, n_trials in 1 .. 2^31-1,
  *                      no NaN (-> ARA_ERR_VALUE).
  *   h_return_periods   host [n_rp], 1 <= n_rp <= 16.
@@ -214,7 +218,8 @@ ara_status ara_pml_tvar(const double *d_ylt, int64_t n_trials, const double *h_r
                         double *h_pml, double *h_tvar, void *hip_stream);
 
 /* A pool of ELTs resident on the device, from which layers are built on the
- * GPU (for ad hoc queries against a resident YET: the ELTs are loaded once,
+ * GPU (for ad hoc queries against a resident YET, the use the paper
+ * motivates in Section I with real-time pricing: the ELTs are loaded once,
  * each query picks some of them and brings its own terms).
  *   h_elt_ids / h_elt_losses / h_elt_sizes  as for ara_create_layer (COPIED).
  *   precision   of every layer built from the pool.
