@@ -4,7 +4,7 @@
 // loss is found exactly by a most-significant-digit radix selection over
 // order-preserving 64-bit keys of the binary64 values (8 passes of 8 bits;
 // every pass builds a 256-bin histogram of the candidates that still share
-// the selected prefix).  The tail mean then adds every value strictly above
+// the selected prefix, and the next launch picks the bin holding the rank).  The tail mean then adds every value strictly above
 // the selected one with a deterministic tree (fixed grid, fixed order) and
 // the ties at the selected value as (k - count) * value, all in binary64.
 // Many YLTs of the same length are handled by the same launches (one grid
@@ -20,7 +20,7 @@ namespace {
 constexpr int kMaxRp = 16;
 constexpr int kMaxYlt = 64;
 constexpr int kMaxSel = kMaxRp * kMaxYlt;
-constexpr int kSumBlocks = 64;
+constexpr int kSumBlocks = 512;
 constexpr int kThreads = 256;
 
 struct SelState {
@@ -48,89 +48,230 @@ struct TailSizes {
     long long k[kMaxRp];
 };
 
-// selection s = y * n_rp + r
-__global__ void k_sel_init(SelState *st, TailSizes k, int n_rp, int n_sel, unsigned *hist, int *nan_flag) {
-    for (int s = threadIdx.x; s < n_sel; s += blockDim.x) st[s] = SelState{0ULL, 0ULL, k.k[s % n_rp], k.k[s % n_rp]};
-    for (int i = threadIdx.x; i < n_sel * 256; i += blockDim.x) hist[i] = 0u;
-    if (threadIdx.x == 0) *nan_flag = 0;
+// The selection state for pass p lives in st[p] (st[kPasses]: the final
+// one) and pass p's histogram in hist[p]: each launch derives the previous
+// pass's pick from its histogram itself, so no launch reads a state that a
+// block of the same launch writes.  The histograms start at zero (cleared
+// when the scratch is allocated) and every call leaves them at zero: the
+// launch two after the last reader of hist[p] clears it (the tail sum clears
+// hist[6], the finishing kernel hist[7]).  The NaN flag is set by the first
+// pass and moved to the results and cleared by the second.
+constexpr int kPasses = 8;
+
+// Clears the histogram rows of YLT yi in hist[p] (block x == 0 of each row).
+__device__ __forceinline__ void clear_rows(unsigned *__restrict__ hist, int p, int n_sel, int yi, int n_rp) {
+    if (blockIdx.x != 0) return;
+    unsigned *row = hist + ((size_t)p * n_sel + (size_t)yi * n_rp) * 256;
+    for (int i = threadIdx.x; i < n_rp * 256; i += blockDim.x) row[i] = 0u;
 }
 
-// grid: (x blocks over the trials, one row per YLT)
-__global__ __launch_bounds__(kThreads) void k_sel_hist(YltPtrs ylts, long long n, const SelState *__restrict__ st,
-                                                       int n_rp, int shift, unsigned *__restrict__ hist, int *nan_flag) {
+// Results go straight to pinned host memory, with system-scope stores.
+__device__ __forceinline__ void store_host(double *p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void store_host(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// One wave applies a pass's pick: lane l holds bins 4l .. 4l+3, a shuffle
+// suffix sum gives every bin the count of candidates at or above it, and the
+// one bin whose range holds rank k_rem is chosen.
+__device__ SelState pick_wave(SelState x, const unsigned *__restrict__ h, int shift) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint4 c = *reinterpret_cast<const uint4 *>(h + 4 * lane);
+    const unsigned long long tot = (unsigned long long)c.x + c.y + c.z + c.w;
+    unsigned long long suf = tot;  // candidates in bins >= 4 * lane
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long u = __shfl_down(suf, d, 64);
+        if (lane + d < 64) suf += u;
+    }
+    const unsigned cnt[4] = {c.x, c.y, c.z, c.w};
+    unsigned long long at = suf;  // candidates in bins >= 4 * lane + v
+    int chosen = -1;
+    unsigned long long above = 0;
+    const unsigned long long k_rem = (unsigned long long)x.k_rem;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const unsigned long long up = at - cnt[v];  // bins above 4 * lane + v
+        if (at >= k_rem && up < k_rem) {
+            chosen = 4 * lane + v;
+            above = up;
+        }
+        at = up;
+    }
+    // exactly one lane holds the chosen bin (k_rem never exceeds the candidates)
+    const unsigned long long owner = __ballot(chosen >= 0);
+    const int src = owner ? __builtin_ctzll(owner) : 0;
+    const int cb = __shfl(chosen, src, 64);
+    const unsigned long long ab = __shfl(above, src, 64);
+    if (cb >= 0) {
+        x.k_rem -= (long long)ab;
+        x.prefix |= ((unsigned long long)cb) << shift;
+        x.mask |= 255ULL << shift;
+    }
+    return x;
+}
+
+// Loads into s[] the selections' states for pass `pass` (st[pass]): for the
+// first pass the start state (tail sizes from the arguments), else the state before the previous pass with
+// that pass's pick applied from its histogram.  Waves take the selections in
+// turn; block 0 stores st[pass] for the finishing kernel.  A launch reads
+// st[pass - 1] and writes st[pass] only, so no block reads what another
+// block of the same launch writes.
+__device__ void load_states(SelState *__restrict__ st, const unsigned *__restrict__ hist, const TailSizes &tk,
+                            int yi, int n_rp, int n_sel, int pass, SelState *s) {
+    const int wave = (int)(threadIdx.x >> 6), n_wave = (int)(blockDim.x >> 6);
+    for (int r = wave; r < n_rp; r += n_wave) {
+        const int sel = yi * n_rp + r;
+        SelState x;
+        if (pass == 0) {
+            x = SelState{0ULL, 0ULL, tk.k[r], tk.k[r]};
+            if (blockIdx.x == 0 && (threadIdx.x & 63u) == 0) st[sel] = x;
+        } else {
+            x = st[(size_t)(pass - 1) * n_sel + sel];
+            x = pick_wave(x, hist + ((size_t)(pass - 1) * n_sel + sel) * 256, 64 - 8 * pass);
+            if (blockIdx.x == 0 && (threadIdx.x & 63u) == 0) st[(size_t)pass * n_sel + sel] = x;
+        }
+        if ((threadIdx.x & 63u) == 0) s[r] = x;
+    }
+}
+
+// A thread's share of a YLT per round: kPer values TH apart (TH threads per
+// block), all loaded before any is used, so their latencies overlap.
+constexpr int kPer = 8;
+constexpr int kHistThreads = 1024;
+constexpr long long kChunk = (long long)kThreads * kPer;
+constexpr long long kHistChunk = (long long)kHistThreads * kPer;
+
+template <int TH>
+__device__ __forceinline__ void load_chunk(const double *__restrict__ y, long long n, long long c0, double (&v)[kPer]) {
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const long long i = c0 + (long long)j * TH + threadIdx.x;
+        v[j] = i < n ? y[i] : 0.0;
+    }
+}
+
+// grid: (x blocks over the trials, one row per YLT).  A thread counts a run
+// of its values that fall into one bin in a register and adds the run to the
+// LDS histogram when the bin changes (the first passes see few bins).
+// Selections of a YLT that still share their prefix (all of them in the
+// first pass) have the same histogram: it is counted once.  Blocks are
+// large, so that few of them add into each global histogram (those atomics
+// are slow when many blocks hit the same bins).
+__global__ __launch_bounds__(kHistThreads) void k_sel_hist(YltPtrs ylts, long long n, SelState *__restrict__ st,
+                                                           TailSizes tk, int n_rp, int n_sel, int pass,
+                                                           unsigned *__restrict__ hist, int *nan_flag,
+                                                           int *host_nan) {
     __shared__ unsigned h[kMaxRp * 256];
     __shared__ SelState s[kMaxRp];
+    __shared__ int same_as[kMaxRp];  // first selection with the same prefix
     const int yi = blockIdx.y;
+    const int shift = 56 - 8 * pass;
     const double *__restrict__ y = ylts.p[yi];
+    const long long stride = (long long)gridDim.x * kHistChunk;
+    long long c0 = (long long)blockIdx.x * kHistChunk;
+    double v[kPer];
+    load_chunk<kHistThreads>(y, n, c0, v);  // in flight while the previous pick is applied
     for (int i = threadIdx.x; i < n_rp * 256; i += blockDim.x) h[i] = 0u;
-    if (threadIdx.x < n_rp) s[threadIdx.x] = st[yi * n_rp + threadIdx.x];
+    load_states(st, hist, tk, yi, n_rp, n_sel, pass, s);
+    if (pass >= 2) clear_rows(hist, pass - 2, n_sel, yi, n_rp);
+    if (pass == 1 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        store_host(host_nan, *nan_flag);
+        *nan_flag = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)n_rp) {
+        int f = (int)threadIdx.x;
+        for (int q = 0; q < (int)threadIdx.x; ++q)
+            if (s[q].mask == s[threadIdx.x].mask && s[q].prefix == s[threadIdx.x].prefix) {
+                f = q;
+                break;
+            }
+        same_as[threadIdx.x] = f;
+    }
     __syncthreads();
     int saw_nan = 0;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const double v = y[i];
-        saw_nan |= (v != v);
-        const unsigned long long key = order_key(v);
-        const unsigned bin = (unsigned)((key >> shift) & 255ULL);
-        for (int r = 0; r < n_rp; ++r)
-            if ((key & s[r].mask) == s[r].prefix) atomicAdd(&h[r * 256 + bin], 1u);
+    while (c0 < n) {
+        const long long rest = n - c0 - threadIdx.x;  // values of this thread in the chunk: j * kHistThreads < rest
+        double w[kPer];
+        const long long c1 = c0 + stride;
+        if (c1 < n) load_chunk<kHistThreads>(y, n, c1, w);  // the next chunk, in flight while this one is counted
+        for (int r = 0; r < n_rp; ++r) {
+            if (same_as[r] != r) continue;
+            const unsigned long long mask = s[r].mask, prefix = s[r].prefix;
+            unsigned run_bin = 0u, run = 0u;
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                if ((long long)j * kHistThreads >= rest) continue;
+                const unsigned long long key = order_key(v[j]);
+                if ((key & mask) != prefix) continue;
+                const unsigned bin = (unsigned)((key >> shift) & 255ULL);
+                if (run != 0u && bin != run_bin) {
+                    atomicAdd(&h[r * 256 + run_bin], run);
+                    run = 0u;
+                }
+                run_bin = bin;
+                ++run;
+            }
+            if (run != 0u) atomicAdd(&h[r * 256 + run_bin], run);
+        }
+        if (pass == 0) {
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) saw_nan |= ((long long)j * kHistThreads < rest) & (v[j] != v[j]);
+        }
+        c0 = c1;
+        if (c0 < n) {
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) v[j] = w[j];
+        }
     }
     if (saw_nan) atomicOr(nan_flag, 1);
     __syncthreads();
-    for (int i = threadIdx.x; i < n_rp * 256; i += blockDim.x)
-        if (h[i]) atomicAdd(&hist[(yi * n_rp) * 256 + i], h[i]);
+    unsigned *hp = hist + ((size_t)pass * n_sel + (size_t)yi * n_rp) * 256;
+    for (int i = threadIdx.x; i < n_rp * 256; i += blockDim.x) {
+        const unsigned c = h[same_as[i >> 8] * 256 + (i & 255)];
+        if (c) atomicAdd(&hp[i], c);
+    }
 }
 
-// one block per selection: the 256 bins are summed from the top in LDS and
-// the bin holding the selection's rank is picked; the histogram row is then
-// cleared for the next pass
-__global__ __launch_bounds__(256) void k_sel_pick(SelState *st, int shift, unsigned *hist) {
-    __shared__ long long suf[256];  // suf[b] = count of bins b..255
-    __shared__ int chosen;
-    const int s = blockIdx.x;
-    const int b = threadIdx.x;
-    unsigned *h = hist + (size_t)s * 256;
-    suf[b] = h[b];
-    if (b == 0) chosen = 0;  // unreachable fallback: k_rem never exceeds the candidates
-    __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {  // inclusive suffix sum, Hillis-Steele
-        const long long add = b + d < 256 ? suf[b + d] : 0;
-        __syncthreads();
-        suf[b] += add;
-        __syncthreads();
-    }
-    const long long k_rem = st[s].k_rem;
-    const long long above = b < 255 ? suf[b + 1] : 0;  // candidates in bins above b
-    if (suf[b] >= k_rem && above < k_rem) chosen = b;  // exactly one bin satisfies this
-    __syncthreads();
-    if (b == 0) {
-        SelState x = st[s];
-        const int c = chosen;
-        x.k_rem -= c < 255 ? suf[c + 1] : 0;
-        x.prefix |= ((unsigned long long)c) << shift;
-        x.mask |= 255ULL << shift;
-        st[s] = x;
-    }
-    h[b] = 0u;
-}
-
-// grid: (kSumBlocks, one row per YLT)
-__global__ __launch_bounds__(kThreads) void k_tail_sum(YltPtrs ylts, long long n, const SelState *__restrict__ st,
-                                                       int n_rp, double *__restrict__ psum,
+// grid: (kSumBlocks, one row per YLT).  Applies the last pass's pick (the
+// selected key is then exact) and sums every value strictly above it.
+__global__ __launch_bounds__(kThreads) void k_tail_sum(YltPtrs ylts, long long n, SelState *__restrict__ st, TailSizes tk,
+                                                       int n_rp, int n_sel, unsigned *__restrict__ hist,
+                                                       double *__restrict__ psum,
                                                        unsigned long long *__restrict__ pcnt) {
     __shared__ double ssum[kThreads];
     __shared__ unsigned long long scnt[kThreads];
+    __shared__ SelState s[kMaxRp];
     const int yi = blockIdx.y;
     const double *__restrict__ y = ylts.p[yi];
+    const long long stride = (long long)gridDim.x * kChunk;
+    double v[kPer];
+    long long held = (long long)blockIdx.x * kChunk;  // the chunk in v
+    load_chunk<kThreads>(y, n, held, v);
+    load_states(st, hist, tk, yi, n_rp, n_sel, kPasses, s);
+    clear_rows(hist, kPasses - 2, n_sel, yi, n_rp);
+    __syncthreads();
     for (int r = 0; r < n_rp; ++r) {
         const int sel = yi * n_rp + r;
-        const unsigned long long thr = st[sel].prefix;
+        const unsigned long long thr = s[r].prefix;
         double acc = 0.0;
         unsigned long long cnt = 0;
-        for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-            const double v = y[i];
-            if (order_key(v) > thr) {
-                acc += v;
-                ++cnt;
+        for (long long c0 = (long long)blockIdx.x * kChunk; c0 < n; c0 += stride) {
+            if (c0 != held) {
+                load_chunk<kThreads>(y, n, c0, v);
+                held = c0;
+            }
+            const long long rest = n - c0 - threadIdx.x;
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                if ((long long)j * kThreads < rest && order_key(v[j]) > thr) {
+                    acc += v[j];
+                    ++cnt;
+                }
             }
         }
         ssum[threadIdx.x] = acc;
@@ -154,10 +295,12 @@ __global__ __launch_bounds__(kThreads) void k_tail_sum(YltPtrs ylts, long long n
 // one block per selection; the partial sums of the kSumBlocks blocks are
 // added with a fixed tree, so the result does not depend on timing
 __global__ __launch_bounds__(kSumBlocks) void k_tail_finish(const SelState *st, const double *psum,
-                                                            const unsigned long long *pcnt, double *out) {
+                                                            const unsigned long long *pcnt,
+                                                            unsigned *__restrict__ hist7, double *host_out) {
     __shared__ double ssum[kSumBlocks];
     __shared__ unsigned long long scnt[kSumBlocks];
     const int s = blockIdx.x;
+    if (threadIdx.x < 256) hist7[(size_t)s * 256 + threadIdx.x] = 0u;
     ssum[threadIdx.x] = psum[(size_t)s * kSumBlocks + threadIdx.x];
     scnt[threadIdx.x] = pcnt[(size_t)s * kSumBlocks + threadIdx.x];
     __syncthreads();
@@ -172,18 +315,22 @@ __global__ __launch_bounds__(kSumBlocks) void k_tail_finish(const SelState *st, 
         const double pml = key_value(st[s].prefix);
         const long long k = st[s].k;
         const double ties = (double)(k - (long long)scnt[0]) * pml;
-        out[2 * s] = pml;
-        out[2 * s + 1] = (ssum[0] + ties) / (double)k;
+        store_host(host_out + 2 * s, pml);
+        store_host(host_out + 2 * s + 1, (ssum[0] + ties) / (double)k);
     }
 }
 
-// Library-owned scratch per device (device memory and a pinned host buffer
-// for the results); ara_pml_tvar is synchronous and holds the device's lock
-// for the duration of a call.
+// Library-owned scratch per device: device memory and a pinned host buffer
+// that the finishing kernels write the results into.  ara_pml_tvar is
+// synchronous and holds the device's lock for the duration of a call.  A
+// call that fails after its first launch marks the scratch dirty, and the
+// next call clears the histograms and the flag before it starts.
 struct Scratch {
     std::mutex mu;
     void *d = nullptr;
-    void *h = nullptr;
+    void *h = nullptr;   // host address
+    void *hd = nullptr;  // its device address
+    bool dirty = false;
 };
 
 Scratch &scratch_for(int dev) {
@@ -201,16 +348,23 @@ hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n
     if (e != hipSuccess) return e;
     Scratch &sc = scratch_for(dev);
     std::lock_guard<std::mutex> g(sc.mu);
-    // layout: result (nan flag, then PML/TVaR pairs) | state | hist | psum | pcnt
+    // device layout: nan flag (16 B) | states per pass | histograms per pass | psum | pcnt
+    // host layout:   nan flag (16 B) | PML/TVaR pairs
     const size_t res_bytes = 16 + sizeof(double) * 2 * kMaxSel;
-    const size_t off_state = res_bytes;
-    const size_t off_hist = off_state + sizeof(SelState) * kMaxSel;
-    const size_t off_psum = off_hist + sizeof(unsigned) * 256 * kMaxSel;
+    const size_t off_state = 16;
+    const size_t off_hist = off_state + sizeof(SelState) * (kPasses + 1) * kMaxSel;
+    const size_t off_psum = off_hist + sizeof(unsigned) * 256 * kPasses * kMaxSel;
     const size_t off_pcnt = off_psum + sizeof(double) * kSumBlocks * kMaxSel;
     const size_t total = off_pcnt + sizeof(unsigned long long) * kSumBlocks * kMaxSel;
     if (!sc.d) {
         e = hipMalloc(&sc.d, total);
         if (e != hipSuccess) {
+            sc.d = nullptr;
+            return e;
+        }
+        e = hipMemset(sc.d, 0, off_psum);  // flag, states and histograms start at zero
+        if (e != hipSuccess) {
+            (void)hipFree(sc.d);
             sc.d = nullptr;
             return e;
         }
@@ -221,41 +375,50 @@ hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n
             sc.h = nullptr;
             return e;
         }
+        e = hipHostGetDevicePointer(&sc.hd, sc.h, 0);
+        if (e != hipSuccess) {
+            (void)hipHostFree(sc.h);
+            sc.h = nullptr;
+            return e;
+        }
     }
     char *base = static_cast<char *>(sc.d);
     int *nan_flag = reinterpret_cast<int *>(base);
-    double *out = reinterpret_cast<double *>(base + 16);
     SelState *st = reinterpret_cast<SelState *>(base + off_state);
     unsigned *hist = reinterpret_cast<unsigned *>(base + off_hist);
     double *psum = reinterpret_cast<double *>(base + off_psum);
     unsigned long long *pcnt = reinterpret_cast<unsigned long long *>(base + off_pcnt);
+    int *host_nan = static_cast<int *>(sc.hd);
+    double *host_out = reinterpret_cast<double *>(static_cast<char *>(sc.hd) + 16);
     const int n_sel = n_ylt * n_rp;
 
+    if (sc.dirty) {
+        if ((e = hipMemsetAsync(nan_flag, 0, 16, s)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(hist, 0, off_psum - off_hist, s)) != hipSuccess) return e;
+        sc.dirty = false;
+    }
     YltPtrs yp{};
     for (int i = 0; i < n_ylt; ++i) yp.p[i] = d_ylts[i];
     // tail sizes travel as a kernel argument (no host-to-device copy)
     TailSizes tk{};
     for (int r = 0; r < n_rp; ++r) tk.k[r] = (long long)h_k[r];
-    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(1024), 0, s, st, tk, n_rp, n_sel, hist, nan_flag);
-    long long gx = (n + kThreads - 1) / kThreads;
-    const long long cap = n_ylt > 8 ? 64 : 512;
+    long long gx = (n + kHistChunk - 1) / kHistChunk;
+    const long long cap = n_ylt > 8 ? 32 : 256;
     if (gx > cap) gx = cap;
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = 56 - 8 * pass;
-        hipLaunchKernelGGL(k_sel_hist, dim3((unsigned)gx, n_ylt), dim3(kThreads), 0, s, yp, (long long)n, st, n_rp, shift,
-                           hist, nan_flag);
-        hipLaunchKernelGGL(k_sel_pick, dim3(n_sel), dim3(256), 0, s, st, shift, hist);
-    }
-    hipLaunchKernelGGL(k_tail_sum, dim3(kSumBlocks, n_ylt), dim3(kThreads), 0, s, yp, (long long)n, st, n_rp, psum, pcnt);
-    hipLaunchKernelGGL(k_tail_finish, dim3(n_sel), dim3(kSumBlocks), 0, s, st, psum, pcnt, out);
+    sc.dirty = true;  // until the call has run to its end
+    for (int pass = 0; pass < kPasses; ++pass)
+        hipLaunchKernelGGL(k_sel_hist, dim3((unsigned)gx, n_ylt), dim3(kHistThreads), 0, s, yp, (long long)n, st, tk,
+                           n_rp, n_sel, pass, hist, nan_flag, host_nan);
+    hipLaunchKernelGGL(k_tail_sum, dim3(kSumBlocks, n_ylt), dim3(kThreads), 0, s, yp, (long long)n, st, tk, n_rp, n_sel,
+                       hist, psum, pcnt);
+    hipLaunchKernelGGL(k_tail_finish, dim3(n_sel), dim3(kSumBlocks), 0, s, st + (size_t)kPasses * n_sel, psum, pcnt,
+                       hist + (size_t)(kPasses - 1) * n_sel * 256, host_out);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // one copy of the flag and the results into pinned memory
-    const size_t got = 16 + sizeof(double) * 2 * (size_t)n_sel;
-    if ((e = hipMemcpyAsync(sc.h, sc.d, got, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    sc.dirty = false;
     const char *hb = static_cast<const char *>(sc.h);
-    *h_nan = *reinterpret_cast<const int *>(hb);
-    const double *ho = reinterpret_cast<const double *>(hb + 16);
+    *h_nan = *reinterpret_cast<const volatile int *>(hb);
+    const volatile double *ho = reinterpret_cast<const volatile double *>(hb + 16);
     for (int i = 0; i < 2 * n_sel; ++i) h_out[i] = ho[i];
     return hipSuccess;
 }
