@@ -263,6 +263,39 @@ def test_pml_tvar_ties_zeros_negatives():
     assert np.allclose(gt, ot, rtol=1e-12, atol=1e-300)
 
 
+def test_pml_tvar_call_sequence():
+    """Calls of different shapes in a row (1, 64 and 5 YLTs; 1 to 16 return
+    periods; one call rejected for a NaN in between) each match the oracle:
+    nothing of one call's selection state or NaN flag reaches the next."""
+    rng = np.random.default_rng(11)
+    T = 20_011
+    ylts = [np.round(rng.lognormal(12, 1.5, T), 2) for _ in range(64)]
+    for y in ylts[::3]:
+        y[rng.integers(0, T, 400)] = 0.0
+    dev = [torch.from_numpy(y).cuda() for y in ylts]
+    shapes = [(1, [250.0]), (64, [1.0, 2.0, 10.0, 100.0, 250.0, 1000.0, 3.0, 7.0, 11.0, 13.0, 17.0, 19.0, 23.0,
+                                  29.0, 31.0, 20011.0]),
+              (5, [100.0, 250.0]), (1, [2.0, 5.0, 20011.0])]
+    for i, (n, Ns) in enumerate(shapes):
+        if i == 2:
+            bad = dev[0].clone()
+            bad[17] = float("nan")
+            with pytest.raises(L.AraError) as ei:
+                A.pml_tvar(bad, [100.0])
+            assert ei.value.name == "ARA_ERR_VALUE"
+        if n == 1:
+            gp, gt = A.pml_tvar(dev[i], Ns)
+            gp, gt = gp[None, :], gt[None, :]
+            src = [ylts[i]]
+        else:
+            gp, gt = A.pml_tvar_many(dev[:n], Ns)
+            src = ylts[:n]
+        for j, y in enumerate(src):
+            op, ot = oracle.pml_tvar(y, Ns)
+            assert np.array_equal(gp[j], op), (i, j)
+            assert np.allclose(gt[j], ot, rtol=1e-12, atol=0.0), (i, j)
+
+
 def test_pml_tvar_errors():
     y = torch.ones(10, dtype=torch.float64, device="cuda")
     with pytest.raises(L.AraError) as ei:
