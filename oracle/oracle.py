@@ -5,6 +5,12 @@ import this module.  It wraps the plain sequential float64 C implementation in
 ``ara_oracle.c`` (Section III of the paper: Algorithm 1 and its four steps) and
 adds the risk metrics read from the Year Loss Table.
 
+Roll-up (the paper nests layers in programs and programs in a portfolio,
+Section III, without saying how their results combine; the reading used
+here): the year loss of a program in a trial is the sum of its layers' year
+losses in that trial, added in binary64 in layer order starting from 0; a
+portfolio rolls up its programs the same way.
+
 Risk metrics (the paper names PML and TVaR without defining them; the
 reading used here): for a return period of N years over T trials, with
 k = floor(T / N) >= 1,
@@ -127,3 +133,22 @@ def pml_tvar(ylt: np.ndarray, return_periods: Sequence[float]):
         pml.append(float(y[k - 1]))
         tvar.append(math.fsum(y[:k].tolist()) / k)
     return np.array(pml), np.array(tvar)
+
+
+def rollup(ylts: Sequence[np.ndarray], groups: Sequence[int], n_groups: int):
+    """Year loss tables of n_groups groups (programs, or a portfolio): group g
+    is the trial-by-trial sum of the input tables l with groups[l] == g, added
+    in increasing l from 0.0 (a group without inputs is all zero)."""
+    if len(ylts) != len(groups):
+        raise OracleError("one group index per input table")
+    T = len(ylts[0]) if len(ylts) else 0
+    out = [np.zeros(T, np.float64) for _ in range(n_groups)]
+    for l, g in enumerate(groups):
+        if not 0 <= g < n_groups:
+            raise OracleError(f"group index {g} outside 0 .. {n_groups - 1}")
+        y = np.asarray(ylts[l], dtype=np.float64)
+        if len(y) != T:
+            raise OracleError("input tables differ in length")
+        out[g] = out[g] + y  # one binary64 addition per trial
+    return out
+

@@ -362,3 +362,71 @@ def test_occ_max_closed_forms_and_bounds():
     for i in range(len(off) - 1):
         rng.shuffle(pid[off[i]:off[i + 1]])
     assert np.array_equal(_run(pid, off, C, lay, want_occ_max=True)["occ_max"], r["occ_max"])
+
+
+# ----------------------------------------------------------------------------- roll-up of layers into programs
+def _golden_layer2(g):
+    l2 = g["rollup"]["layer2"]
+    return W.LayerSpec([np.array(e["ids"], np.int32) for e in l2["elts"]],
+                       [np.array(e["losses"], np.float64) for e in l2["elts"]],
+                       np.array([e["ret"] for e in l2["elts"]], np.float64),
+                       np.array([e["lim"] for e in l2["elts"]], np.float64),
+                       l2["occ_ret"], l2["occ_lim"], l2["agg_ret"], l2["agg_lim"])
+
+
+def test_rollup_worked_example():
+    """Hand-worked second layer, program and portfolio (integers: exact)."""
+    g = json.load(open(GOLD))
+    ids, off = _flatten(g["trials"])
+    y1 = _run(ids, off, g["catalog_size"], _golden_layer(g))["ylt"]
+    r2 = _run(ids, off, g["catalog_size"], _golden_layer2(g))
+    ru = g["rollup"]
+    assert r2["occ_sum"].tolist() == ru["layer2"]["occ_sum"]
+    assert r2["ylt"].tolist() == ru["layer2"]["ylt"]
+    p1, p2 = oracle.rollup([y1, r2["ylt"], r2["ylt"]], [0, 0, 1], 2)
+    assert p1.tolist() == ru["program_p1_ylt"]
+    assert p2.tolist() == ru["program_p2_ylt"]
+    (pf,) = oracle.rollup([p1, p2], [0, 0], 1)
+    assert pf.tolist() == ru["portfolio_ylt"]
+    for N, (pml, tvar) in ru["program_p1_pml_tvar"].items():
+        op, ot = oracle.pml_tvar(p1, [float(N)])
+        assert (op[0], ot[0]) == (pml, tvar)
+
+
+def test_rollup_of_open_layers_is_the_union_layer():
+    """Open terms and integer losses: the roll-up of layers over ELT sets A and
+    B is the year loss of one layer over A and B together, exactly (an
+    independent route through the pass itself)."""
+    C = 4000
+    ids, off, lay = W.random_case(21, 300, 120.0, C, 7, 700, integer_losses=True, max_int_loss=500, terms="open")
+    parts = [(0, 2), (2, 3), (3, 7)]
+    ylts = []
+    for a, b in parts:
+        part = W.LayerSpec(lay.elt_ids[a:b], lay.elt_losses[a:b], lay.ret[a:b], lay.lim[a:b], 0.0, np.inf, 0.0, np.inf)
+        ylts.append(_run(ids, off, C, part)["ylt"])
+    whole = _run(ids, off, C, lay)["ylt"]
+    (prog,) = oracle.rollup(ylts, [0, 0, 0], 1)
+    assert np.array_equal(prog, whole)
+
+
+def test_rollup_groups_and_tvar_subadditivity():
+    """A group without inputs is zero, a one-input group is its input, and the
+    mean of the k largest year losses of a sum is at most the sum of the
+    inputs' means (true of any top-k mean)."""
+    rng = np.random.default_rng(5)
+    T = 4000
+    ylts = []
+    for i in range(5):
+        y = rng.lognormal(11, 1.5, T)
+        y[rng.random(T) < 0.5] = 0.0
+        ylts.append(y)
+    groups = [1, 1, 3, 1, 1]
+    out = oracle.rollup(ylts, groups, 4)
+    assert not out[0].any() and not out[2].any()
+    assert np.array_equal(out[3], ylts[2])
+    Ns = [2.0, 10.0, 100.0, 250.0, 1000.0]
+    _, tsum = oracle.pml_tvar(out[1], Ns)
+    parts = [oracle.pml_tvar(ylts[i], Ns)[1] for i in (0, 1, 3, 4)]
+    assert np.all(tsum <= np.sum(parts, axis=0) * (1 + 1e-12))
+    with pytest.raises(oracle.OracleError):
+        oracle.rollup(ylts, [0, 0, 0, 0, 4], 4)
