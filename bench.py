@@ -171,11 +171,29 @@ def batch_leg(A, W, torch, n_trials, steps, precision="fp64"):
            "launch_config": list(batch.launch_config), "record_bytes": batch.device_bytes,
            "batch_build_ms": batch_build_ms, "first_run_ms_incl_tuning": first_run_ms,
            "layer_build_s_total": layer_build_s, "bitwise_equal_to_sequential": bool(same)}
+    # programs of 8 layers each, then the portfolio of the 8 programs, and
+    # their PML/TVaR (100 and 250 years)
+    progs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in range(8)]
+    pfolio = [torch.empty(T, dtype=torch.float64, device="cuda")]
+    groups = [l * 8 // len(layers) for l in range(len(layers))]
+
+    def roll():
+        A.rollup(outs, groups, 8, out=progs)
+        A.rollup(progs, [0] * 8, 1, out=pfolio)
+
+    roll_ms = timed(roll, 5)
+    ppml, ptvar = A.pml_tvar_many(progs + pfolio, [100.0, 250.0])
+    roll_bytes = (len(layers) + 8 + 8 + 1) * T * 8
+    res["rollup"] = {"programs": 8, "layers_per_program": len(layers) // 8, "ms": round(roll_ms, 4),
+                     "gbps": round(roll_bytes / (roll_ms * 1e-3) / 1e9, 1),
+                     "program_pml": ppml[:8].tolist(), "program_tvar": ptvar[:8].tolist(),
+                     "portfolio_pml": ppml[8].tolist(), "portfolio_tvar": ptvar[8].tolist()}
+    log(f"batch leg: roll-up into 8 programs and a portfolio {roll_ms:.3f} ms")
     batch.close()
     for l in layers:
         l.close()
     yet.close()
-    del t_ids, t_off, outs, seq
+    del t_ids, t_off, outs, seq, progs, pfolio
     torch.cuda.empty_cache()
     return res
 
@@ -328,6 +346,22 @@ def main():
         for _ in range(5):
             A.pml_tvar(ylt, rps)
         extras["pml_tvar_ms"] = round((time.perf_counter() - t) * 200, 4)
+        # a plain read-only pass over the same 4 GB: the YET validation that
+        # ara_create_yet runs (every ID read once with 16-byte loads, a range
+        # check), timed on the host around the synchronous create call
+        A.Yet(t_ids, None, T, wl.yet.catalog_size, K).close()
+        ms_rd = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            A.Yet(t_ids, None, T, wl.yet.catalog_size, K).close()
+            ms_rd.append((time.perf_counter() - t0) * 1e3)
+        rd_ms = sorted(ms_rd)[2]
+        rd_gbps = t_ids.numel() * 4 / (rd_ms * 1e-3) / 1e9
+        extras["hbm_read_probe"] = {"what": "YET validation in ara_create_yet: 4.0e9 bytes read once, host clock incl. "
+                                            "the call", "ms": round(rd_ms, 4), "gbps": round(rd_gbps, 1),
+                                    "trial_pass_frac_of_it": round(achieved / rd_gbps, 3)}
+        log(f"read probe: {rd_gbps:.0f} GB/s; the trial pass reaches {achieved / rd_gbps:.2f} of it")
 
     lay_layout, lay_prec = lay.layout, lay.precision
     del t_ids

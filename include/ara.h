@@ -257,6 +257,25 @@ ara_status ara_pml_tvar_many(const double *const *d_ylts, int32_t n_ylts, int64_
                              const double *h_return_periods, int32_t n_rp, double *h_pml, double *h_tvar,
                              void *hip_stream);
 
+/* Roll-up of year loss tables into programs, or of programs into a
+ * portfolio.  Section III nests layers in programs and programs in a
+ * portfolio and leaves their combination unstated; the reading here: group
+ * g's year loss in a trial is the binary64 sum of the year losses in that
+ * trial of the inputs l with h_group[l] == g, added in increasing l starting
+ * from 0 (a group without inputs gets zeros).  Rolling the program tables up
+ * again with every h_group entry 0 gives the portfolio.
+ *   d_ylts    n_inputs device pointers to binary64 [n_trials] tables,
+ *             1 <= n_inputs <= ARA_MAX_BATCH.
+ *   h_group   host [n_inputs], each in 0 .. n_groups-1.
+ *   n_groups  1 .. ARA_MAX_BATCH.
+ *   n_trials  0 .. 2^31-1 (0: nothing to do; the table pointers may then be NULL).
+ *   d_out     n_groups caller-owned device pointers to binary64 [n_trials];
+ *             no output may overlap an input or another output
+ *             (ARA_ERR_INVALID_ARG).
+ * ASYNCHRONOUS on hip_stream; the inputs are read once. */
+ara_status ara_rollup(const double *const *d_ylts, int32_t n_inputs, const int32_t *h_group, int32_t n_groups,
+                      int64_t n_trials, double *const *d_out, void *hip_stream);
+
 /* Device bytes a layer holds (for memory admission). */
 size_t ara_layer_device_bytes(ara_layer layer);
 

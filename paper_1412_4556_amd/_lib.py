@@ -50,6 +50,7 @@ SIGNATURES = {
     "ara_pool_free_slots": (_I32, [_P]),
     "ara_create_layer_from_pool": (_I32, [_P, _I32, _P, _P, _P, _D, _D, _D, _D, _P, _P]),
     "ara_pml_tvar_many": (_I32, [_P, _I32, _I64, _P, _I32, _P, _P, _P]),
+    "ara_rollup": (_I32, [_P, _I32, _P, _I32, _I64, _P, _P]),
     "ara_pml_tvar": (_I32, [_P, _I64, _P, _I32, _P, _P, _P]),
     "ara_layer_device_bytes": (_SZ, [_P]),
     "ara_layer_layout": (_I32, [_P]),

@@ -303,6 +303,29 @@ def pml_tvar_many(ylts: Sequence[torch.Tensor], return_periods: Sequence[float],
     return pml, tvar
 
 
+def rollup(ylts: Sequence[torch.Tensor], groups: Sequence[int], n_groups: int, out=None, stream=None):
+    """Year loss tables of n_groups groups: group g is the trial-by-trial sum of
+    ylts[l] for groups[l] == g, in increasing l (ara_rollup); asynchronous."""
+    n = len(ylts)
+    T = ylts[0].numel() if n else 0
+    for y in ylts:
+        _check_out(y, T, "ylt")
+    if out is None:
+        dev = ylts[0].device if n else "cuda"
+        out = [torch.empty(T, dtype=torch.float64, device=dev) for _ in range(max(n_groups, 0))]
+    if len(out) != max(n_groups, 0):
+        raise ValueError("one output table per group")
+    for o in out:
+        _check_out(o, T, "out")
+    ps = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ylts])
+    gs = _np(list(groups), np.int32)
+    if len(gs) != n:
+        raise ValueError("one group index per input table")
+    os_ = (ctypes.c_void_p * max(n_groups, 1))(*[o.data_ptr() for o in out])
+    L.check(L.lib().ara_rollup(ps, n, _vp(gs), int(n_groups), int(T), os_, ctypes.c_void_p(_stream(stream))))
+    return list(out)
+
+
 def yet_from_numpy(ids: np.ndarray, offsets: Optional[np.ndarray], n_trials: int, catalog_size: int,
                    events_per_trial: int = 0, device: str = "cuda") -> Yet:
     """Copy a host YET to the device and register it."""

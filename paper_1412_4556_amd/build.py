@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libara.so")
-SOURCES = ["ara_api.hip", "ara_kernels.hip", "ara_select.hip"]
+SOURCES = ["ara_api.hip", "ara_kernels.hip", "ara_select.hip", "ara_rollup.hip"]
 ARCH = os.environ.get("ARA_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

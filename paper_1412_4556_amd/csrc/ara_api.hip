@@ -961,6 +961,47 @@ ara_status ara_run_layers(ara_yet yet, const ara_layer *layers, double *const *d
     return ARA_OK;
 }
 
+ara_status ara_rollup(const double *const *d_ylts, int32_t n_inputs, const int32_t *h_group, int32_t n_groups,
+                      int64_t n_trials, double *const *d_out, void *hip_stream) {
+    if (!d_ylts || !h_group || !d_out) return fail(ARA_ERR_INVALID_ARG, "NULL pointer");
+    if (n_inputs < 1 || n_inputs > ARA_MAX_BATCH) return fail(ARA_ERR_INVALID_ARG, "n_inputs outside 1 .. ARA_MAX_BATCH");
+    if (n_groups < 1 || n_groups > ARA_MAX_BATCH) return fail(ARA_ERR_INVALID_ARG, "n_groups outside 1 .. ARA_MAX_BATCH");
+    if (n_trials < 0 || n_trials > 2147483647LL) return fail(ARA_ERR_INVALID_ARG, "n_trials outside 0 .. 2^31-1");
+    for (int l = 0; l < n_inputs; ++l) {
+        if (!d_ylts[l] && n_trials > 0) return fail(ARA_ERR_INVALID_ARG, "NULL input table");
+        if (h_group[l] < 0 || h_group[l] >= n_groups) return fail(ARA_ERR_INVALID_ARG, "group index outside 0 .. n_groups-1");
+    }
+    for (int g = 0; g < n_groups; ++g)
+        if (!d_out[g] && n_trials > 0) return fail(ARA_ERR_INVALID_ARG, "NULL output table");
+    if (n_trials == 0) return ARA_OK;
+    // no output may share a byte with an input or with another output
+    const uintptr_t bytes = (uintptr_t)n_trials * sizeof(double);
+    auto overlap = [bytes](const void *a, const void *b) {
+        const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+        return bytes > 0 && x < y + bytes && y < x + bytes;
+    };
+    for (int g = 0; g < n_groups; ++g) {
+        for (int l = 0; l < n_inputs; ++l)
+            if (overlap(d_out[g], d_ylts[l])) return fail(ARA_ERR_INVALID_ARG, "an output table overlaps an input");
+        for (int h = 0; h < g; ++h)
+            if (overlap(d_out[g], d_out[h])) return fail(ARA_ERR_INVALID_ARG, "two output tables overlap");
+    }
+    // inputs ordered by group, each group's in increasing input index
+    ara::RollupTables a{};
+    a.n_groups = n_groups;
+    int q = 0;
+    for (int g = 0; g < n_groups; ++g) {
+        a.first[g] = q;
+        a.out[g] = d_out[g];
+        for (int l = 0; l < n_inputs; ++l)
+            if (h_group[l] == g) a.in[q++] = d_ylts[l];
+    }
+    a.first[n_groups] = q;
+    hipError_t e = ara::launch_rollup(a, n_trials, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "roll-up");
+    return ARA_OK;
+}
+
 static ara_status tail_sizes(int64_t n_trials, const double *h_return_periods, int32_t n_rp, int64_t *k) {
     if (n_trials < 1 || n_trials > 2147483647LL) return fail(ARA_ERR_INVALID_ARG, "n_trials outside 1 .. 2^31-1");
     if (n_rp < 1 || n_rp > 16) return fail(ARA_ERR_INVALID_ARG, "n_rp outside 1 .. 16");

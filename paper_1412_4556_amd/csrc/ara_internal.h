@@ -152,6 +152,16 @@ hipError_t launch_pool_layer(LayerHost &L, const int32_t *d_ids, const void *d_l
 // d[0 .. n) = 0 with a kernel (no memset node if the caller captures a graph)
 hipError_t launch_fill_zero(double *d, int64_t n, hipStream_t s);
 
+// Roll-up (ara_rollup.hip): out[g][i] = sum of in[q][i] for q in
+// first[g] .. first[g+1), added in that order from 0, for every group g.
+struct RollupTables {
+    const double *in[ARA_MAX_BATCH];
+    double *out[ARA_MAX_BATCH];
+    int32_t first[ARA_MAX_BATCH + 1];
+    int32_t n_groups;
+};
+hipError_t launch_rollup(const RollupTables &a, int64_t n, hipStream_t s);
+
 // Selection (ara_select.hip): PML / TVaR of n_ylt YLTs of length n for n_rp
 // tail sizes k[r]; h_out[2 * (y * n_rp + r)] = PML, [... + 1] = TVaR.
 hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n, const int64_t *h_k, int32_t n_rp,

@@ -961,12 +961,42 @@ __global__ void k_hash_filter(const T *__restrict__ occ, int64_t catalog, int32_
         }
 }
 
-__global__ void k_validate_yet(const int32_t *__restrict__ ids, int64_t n, int32_t catalog,
-                               const int64_t *__restrict__ off, int64_t n_trials, int32_t *flags) {
+// One read of every ID: the IDs before the first 16-byte boundary and after
+// the last whole 16-byte granule one by one, the granules with non-temporal
+// 16-byte loads: a wave reads 8 KiB in a row (eight loads in flight per
+// lane), the granules after the last whole 8 KiB chunk one per thread.
+__device__ __forceinline__ uint32_t ids_outside(const int4 v, uint32_t catalog) {
+    return ((uint32_t)v.x >= catalog) | ((uint32_t)v.y >= catalog) | ((uint32_t)v.z >= catalog) |
+           ((uint32_t)v.w >= catalog);
+}
+
+__global__ __launch_bounds__(256) void k_validate_yet(const int32_t *__restrict__ ids, int64_t n, int32_t catalog,
+                                                      const int64_t *__restrict__ off, int64_t n_trials,
+                                                      int32_t *flags) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int bad_id = 0, bad_off = 0;
-    for (int64_t i = tid; i < n; i += stride) bad_id |= ((uint32_t)ids[i] >= (uint32_t)catalog);
+    const uint32_t cat = (uint32_t)catalog;
+    int64_t head = (int64_t)(((16u - ((uint32_t)reinterpret_cast<uintptr_t>(ids) & 15u)) & 15u) >> 2);
+    head = head < n ? head : n;
+    const int64_t body = (n - head) >> 2;  // whole granules after the head
+    const int32_t *g0 = ids + head;
+    uint32_t bad = 0;
+    // whole chunks of kRound * 64 granules (8 KiB), one wave per chunk
+    constexpr int kRound = 8;
+    constexpr int64_t kChunkGranules = (int64_t)kRound * kWave;
+    const int64_t lane = threadIdx.x & (kWave - 1), wave = tid / kWave, n_waves = stride / kWave;
+    const int64_t n_chunks = body / kChunkGranules;
+    for (int64_t c = wave; c < n_chunks; c += n_waves) {
+        int4 v[kRound];
+#pragma unroll
+        for (int r = 0; r < kRound; ++r) v[r] = stream_ids4(g0 + 4 * (c * kChunkGranules + r * kWave + lane));
+#pragma unroll
+        for (int r = 0; r < kRound; ++r) bad |= ids_outside(v[r], cat);
+    }
+    for (int64_t g = n_chunks * kChunkGranules + tid; g < body; g += stride) bad |= ids_outside(stream_ids4(g0 + 4 * g), cat);
+    for (int64_t i = tid; i < head; i += stride) bad |= ((uint32_t)ids[i] >= cat);
+    for (int64_t i = head + 4 * body + tid; i < n; i += stride) bad |= ((uint32_t)ids[i] >= cat);
+    int bad_id = bad != 0u, bad_off = 0;
     if (off) {
         for (int64_t i = tid; i < n_trials; i += stride) bad_off |= (off[i + 1] < off[i]);
         if (tid == 0) bad_off |= (off[0] != 0);
@@ -1123,7 +1153,7 @@ hipError_t launch_fuse(LayerHost &L, const void *d_rows, const int32_t *d_presen
 }
 
 hipError_t launch_validate_yet(const YetView &y, int32_t catalog, int32_t *d_flags, hipStream_t s) {
-    const int grid = cu_count() * 4;
+    const int grid = cu_count() * 8;
     hipLaunchKernelGGL(k_validate_yet, dim3(grid), dim3(256), 0, s, y.ids, y.n_events, catalog, y.offsets, y.n_trials,
                        d_flags);
     return hipGetLastError();

@@ -308,6 +308,32 @@ def test_pml_tvar_errors():
 
 
 # ----------------------------------------------------------------------------- error paths
+@pytest.mark.parametrize("misalign", [0, 1, 2, 3])
+def test_yet_validation_reads_every_id(misalign):
+    """One out-of-range ID is found wherever it sits: before the first 16-byte
+    boundary, in the vector body (in whole 8 KiB chunks and after them) or
+    after the last whole granule; large YETs too."""
+    for n in (1, 3, 7, 203, 4099, 17_000_017):
+        buf = torch.zeros(n + 4, dtype=torch.int32, device="cuda")
+        ids = buf[misalign:misalign + n]
+        assert ids.data_ptr() % 16 == (buf.data_ptr() + 4 * misalign) % 16
+        A.Yet(ids, None, 1, 10, n).close()
+        for pos in sorted({0, 1, 2, 3, n // 2, n - 5, n - 4, n - 3, n - 1}):
+            if not 0 <= pos < n:
+                continue
+            ids[pos] = 10
+            with pytest.raises(L.AraError) as ei:
+                A.Yet(ids, None, 1, 10, n)
+            assert ei.value.name == "ARA_ERR_EVENT_RANGE", (n, pos)
+            ids[pos] = -1
+            with pytest.raises(L.AraError) as ei:
+                A.Yet(ids, None, 1, 10, n)
+            assert ei.value.name == "ARA_ERR_EVENT_RANGE", (n, pos)
+            ids[pos] = 9
+            A.Yet(ids, None, 1, 10, n).close()
+            ids[pos] = 0
+
+
 def test_create_errors():
     ids = torch.tensor([0, 1, 2, 5], dtype=torch.int32, device="cuda")
     with pytest.raises(L.AraError) as ei:
