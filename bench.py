@@ -89,8 +89,11 @@ def time_layer(A, torch, yet, lay, ylt, steps, warmup, rps, with_pml=True):
     return (t1 - t0) * 1e3 / steps, sum(k_ms) / len(k_ms), min(k_ms), res
 
 
-def cpu_baseline(wl, spec, target_s):
-    """The oracle on a bounded sample of the same workload, on the host cores."""
+def cpu_baseline(wl, spec, target_s, gpu_ylt=None, gpu_pml_tvar=None, rps=()):
+    """The oracle on a bounded sample of the same workload, on the host cores;
+    with the GPU's YLT of the timed pass, also the GPU's error on the sample
+    (|y - y_oracle| / G per trial, G the trial's gross looked-up loss) and,
+    when the sample is the whole workload, PML/TVaR against the oracle's."""
     import numpy as np
 
     from oracle import oracle
@@ -102,17 +105,32 @@ def cpu_baseline(wl, spec, target_s):
     def run(n):
         ids, off = W.yet_subset(wl.yet, np.arange(n))
         t = time.perf_counter()
-        oracle.run_layer(ids, off, n, 0, wl.yet.catalog_size, spec, n_threads=threads)
-        return time.perf_counter() - t, int(off[-1])
+        r = oracle.run_layer(ids, off, n, 0, wl.yet.catalog_size, spec, n_threads=threads)
+        return time.perf_counter() - t, int(off[-1]), r
 
-    probe = 2000 * threads
-    dt, ev = run(probe)
+    probe = min(2000 * threads, wl.yet.n_trials)
+    dt, ev, _ = run(probe)
     n = int(min(wl.yet.n_trials, max(probe, probe * target_s / max(dt, 1e-3))))
-    dt, ev = run(n)
-    return {"value": ev * J / dt, "unit": "lookups/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of {wl.yet.n_trials} trials ({ev} trial-events x {J} ELTs), FP64, "
-                      f"OpenMP over trials, {dt:.1f} s incl. direct-table build",
-            "cpu_model": cpu_model(), "seconds": dt}
+    dt, ev, ref = run(n)
+    res = {"value": ev * J / dt, "unit": "lookups/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {n} of {wl.yet.n_trials} trials ({ev} trial-events x {J} ELTs), FP64, "
+                     f"OpenMP over trials, {dt:.1f} s incl. direct-table build",
+           "cpu_model": cpu_model(), "seconds": dt}
+    if gpu_ylt is not None:
+        err = np.abs(gpu_ylt[:n] - ref["ylt"])
+        scaled = err / np.maximum(ref["gross"], 1e-300)
+        pos = ref["ylt"] > 0
+        par = {"trials_compared": n, "max_err_over_gross": float(scaled.max()),
+               "trials_over_1e-12_gross": int((err > 1e-12 * ref["gross"]).sum()),
+               "max_rel_err": float((err[pos] / ref["ylt"][pos]).max()) if pos.any() else 0.0,
+               "bitwise_equal_trials": int((gpu_ylt[:n] == ref["ylt"]).sum())}
+        if n == wl.yet.n_trials and gpu_pml_tvar is not None:
+            op, ot = oracle.pml_tvar(ref["ylt"], rps)
+            gp, gt = gpu_pml_tvar
+            par["pml_max_rel_err"] = float(np.max(np.abs(np.asarray(gp) - op) / np.abs(op)))
+            par["tvar_max_rel_err"] = float(np.max(np.abs(np.asarray(gt) - ot) / np.abs(ot)))
+        res["parity"] = par
+    return res
 
 
 def batch_leg(A, W, torch, n_trials, steps, precision="fp64"):
@@ -298,6 +316,7 @@ def main():
     log(f"layer: {J} ELTs, layout {lay.layout}, precision {lay.precision}, {lay.device_bytes} device bytes")
 
     ms_step, k_ms, k_min, (pml, tvar) = time_layer(A, torch, yet, lay, ylt, args.steps, args.warmup, rps)
+    ylt_host = ylt.cpu().numpy()  # the timed pass's YLT, for the parity check against the oracle
     lookups = float(T) * K * J
     algo_bytes = T * K * 4 + T * 8 + lay.device_bytes
     achieved = algo_bytes / (k_ms * 1e-3) / 1e9
@@ -380,7 +399,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(wl, spec, args.cpu_seconds)
+        cpu = cpu_baseline(wl, spec, args.cpu_seconds, gpu_ylt=ylt_host, gpu_pml_tvar=(pml, tvar), rps=rps)
         log(f"cpu baseline {cpu['value']:.3e} lookups/s on {cpu['cores']} threads")
 
     rec = {
