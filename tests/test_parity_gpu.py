@@ -213,6 +213,32 @@ def test_fixed_length_large_catalog():
         assert (ys[1] > 0).mean() > 0.05
 
 
+def test_largest_catalog():
+    """Event IDs up to 2^31 - 2 (catalogue 2^31 - 1, the largest accepted):
+    the fused table has 2^31 entries and each block-filter bit covers 2^11
+    events; every layout and precision against the oracle."""
+    C = 2**31 - 1
+    rng = np.random.default_rng(47)
+    elt_ids = [np.unique(rng.integers(0, C, 1200)).astype(np.int32)[:1000] for _ in range(3)]
+    elt_ids[0][:2] = [0, C - 1]
+    elt_ids[0] = np.unique(elt_ids[0]).astype(np.int32)
+    losses = [np.round(rng.lognormal(8, 1.5, len(e)), 2) for e in elt_ids]
+    spec = W.LayerSpec(elt_ids, losses, np.full(3, 100.0), np.full(3, 1e6), 50.0, 5e6, 1e3, 1e8)
+    T = 300
+    lens = rng.poisson(40, T)
+    off = np.zeros(T + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    pool = np.concatenate(elt_ids)
+    ids = np.where(rng.random(off[-1]) < 0.5, rng.choice(pool, off[-1]), rng.integers(0, C, off[-1])).astype(np.int32)
+    ids[off[0]:off[0] + 2] = [C - 1, 0]
+    ref = oracle_run(ids, off, T, C, 0, spec)
+    assert (ref["ylt"] > 0).mean() > 0.5
+    for prec, layout in (("fp64", "fused"), ("fp32c", "fused"), ("fp64", "compact"), ("fp64", "sparse")):
+        y = gpu_layer_run(ids, off, T, C, 0, spec, prec, layout)
+        assert_close_to_oracle(y, ref, prec)
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_integer_cases_are_bitwise(prec):
     for seed in (51, 52, 53):
@@ -250,6 +276,26 @@ def test_pml_tvar_permutation(T, N):
     k = T // N
     assert pml[0] == T - k + 1
     assert tvar[0] == T - (k - 1) / 2
+
+
+def test_pml_tvar_largest_size():
+    """The largest accepted YLT, 2^31 - 1 trials (16 GiB), holding 1..T in
+    reverse order: PML_N = T - k + 1 exactly; TVaR_N = T - (k - 1) / 2, exact
+    while the tail sum stays below 2^53, else within binary64 summation error."""
+    T = 2**31 - 1
+    y = torch.arange(T, 0, -1, dtype=torch.float64, device="cuda")
+    Ns = [float(T), 1e6, 100.0, 1.0]
+    pml, tvar = A.pml_tvar(y, Ns)
+    del y
+    torch.cuda.empty_cache()
+    for i, N in enumerate(Ns):
+        k = int(T // N)
+        assert pml[i] == T - k + 1, (N, pml[i])
+        want = T - (k - 1) / 2
+        if k * float(T) < 2.0**53:
+            assert tvar[i] == want, (N, tvar[i])
+        else:
+            assert abs(tvar[i] - want) <= 1e-12 * want, (N, tvar[i], want)
 
 
 def test_pml_tvar_ties_zeros_negatives():
