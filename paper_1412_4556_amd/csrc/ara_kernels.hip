@@ -139,31 +139,82 @@ __device__ __forceinline__ Acc<double> shfl_acc(const Acc<double> &a, int src) {
 __device__ __forceinline__ Acc<float> shfl_acc(const Acc<float> &a, int src) {
     return Acc<float>{__shfl(a.s, src), __shfl(a.c, src)};
 }
-__device__ __forceinline__ Acc<double> shfl_xor_acc(const Acc<double> &a, int m) {
-    return Acc<double>{__shfl_xor(a.s, m)};
-}
-__device__ __forceinline__ Acc<float> shfl_xor_acc(const Acc<float> &a, int m) {
-    return Acc<float>{__shfl_xor(a.s, m), __shfl_xor(a.c, m)};
+
+// Partner of the butterfly step that pairs lane i with lane i ^ M, without
+// the LDS: M = 32 and 16 by the lane-half / row swaps of gfx950, M = 2 and 1
+// by quad permutes; M = 8 and 4 by row rotations, which reach a lane whose
+// value is bitwise that of lane i ^ M at those steps (after the steps 32 and
+// 16 every lane holds the value of all lanes equal to it mod 16, after step 8
+// mod 8, since every combine is commutative).
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kRowRor4 = 0x124, kRowRor8 = 0x128;
+
+template <int M>
+__device__ __forceinline__ int butterfly_partner(int v) {
+    if (M == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (threadIdx.x & 32u) ? r[0] : r[1];
+    } else if (M == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16u) ? r[0] : r[1];
+    } else if (M == 8) {
+        return dpp_i<kRowRor8, 0xf>(v);
+    } else if (M == 4) {
+        return dpp_i<kRowRor4, 0xf>(v);
+    } else if (M == 2) {
+        return dpp_i<kQuadXor2, 0xf>(v);
+    } else {
+        return dpp_i<kQuadXor1, 0xf>(v);
+    }
 }
 
-// Butterfly all-reduce; every combine is commutative, so all lanes end with
-// the same bits.
+template <int M>
+__device__ __forceinline__ double butterfly_partner(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = butterfly_partner<M>((int)(b & 0xffffffffLL));
+    const int hi = butterfly_partner<M>((int)(b >> 32));
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+template <int M>
+__device__ __forceinline__ float butterfly_partner(float x) {
+    return __int_as_float(butterfly_partner<M>(__float_as_int(x)));
+}
+template <int M>
+__device__ __forceinline__ Acc<double> butterfly_partner(const Acc<double> &a) {
+    return Acc<double>{butterfly_partner<M>(a.s)};
+}
+template <int M>
+__device__ __forceinline__ Acc<float> butterfly_partner(const Acc<float> &a) {
+    return Acc<float>{butterfly_partner<M>(a.s), butterfly_partner<M>(a.c)};
+}
+
+// Butterfly all-reduce (partners lane ^ 32, ^ 16, ..., ^ 1, in that order);
+// every combine is commutative, so all lanes end with the same bits.
 template <typename T>
 __device__ __forceinline__ Acc<T> wave_allreduce(Acc<T> a) {
-#pragma unroll
-    for (int m = kWave / 2; m >= 1; m >>= 1) a = Acc<T>::combine(a, shfl_xor_acc(a, m));
+    a = Acc<T>::combine(a, butterfly_partner<32>(a));
+    a = Acc<T>::combine(a, butterfly_partner<16>(a));
+    a = Acc<T>::combine(a, butterfly_partner<8>(a));
+    a = Acc<T>::combine(a, butterfly_partner<4>(a));
+    a = Acc<T>::combine(a, butterfly_partner<2>(a));
+    a = Acc<T>::combine(a, butterfly_partner<1>(a));
     return a;
 }
 
 // Largest value over the wave (exact; every lane ends with it).
 template <typename T>
 __device__ __forceinline__ T wave_max(T x) {
-#pragma unroll
-    for (int m = kWave / 2; m >= 1; m >>= 1) {
-        const T o = __shfl_xor(x, m);
-        x = o > x ? o : x;
-    }
-    return x;
+    T o = butterfly_partner<32>(x);
+    x = o > x ? o : x;
+    o = butterfly_partner<16>(x);
+    x = o > x ? o : x;
+    o = butterfly_partner<8>(x);
+    x = o > x ? o : x;
+    o = butterfly_partner<4>(x);
+    x = o > x ? o : x;
+    o = butterfly_partner<2>(x);
+    x = o > x ? o : x;
+    o = butterfly_partner<1>(x);
+    return o > x ? o : x;
 }
 
 // --------------------------------------------------------------------------------------------
