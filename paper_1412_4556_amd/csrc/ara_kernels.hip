@@ -620,6 +620,8 @@ __global__ __launch_bounds__(1024) void k_trial_pass_events_fused(
     extern __shared__ uint32_t sfilt[];
     load_filters(f, sfilt);
     const int lane = lane_id();
+    // both outputs 32-byte aligned (a missing one counts as aligned)
+    const bool out32 = ((reinterpret_cast<uintptr_t>(cum) | reinterpret_cast<uintptr_t>(net)) & 31u) == 0;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     constexpr int64_t kSpan = (int64_t)G * 4 * kWave;
     const int64_t last_granule = (y.n_events - 1) & ~3LL;  // launched only with n_events >= 1
@@ -665,13 +667,32 @@ __global__ __launch_bounds__(1024) void k_trial_pass_events_fused(
                 }
                 double a_prev = __shfl(Av[3], lane > 0 ? lane - 1 : 0);
                 if (lane == 0) a_prev = carry_net;
+                double nv[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    if ((valid >> (4 * c + v)) & 1u) {
-                        if (cum) cum[p + v] = Sv[v];
-                        if (net) net[p + v] = Av[v] - a_prev;
-                    }
+                    nv[v] = Av[v] - a_prev;
                     a_prev = Av[v];
+                }
+                // a lane's four events in one 32-byte piece of each output:
+                // two 16-byte stores, else one store per event in the trial
+                const uint32_t nib = (valid >> (4 * c)) & 0xfu;
+                if (out32 && nib == 0xfu && (p & 3) == 0) {
+                    if (cum) {
+                        reinterpret_cast<double2 *>(cum + p)[0] = make_double2(Sv[0], Sv[1]);
+                        reinterpret_cast<double2 *>(cum + p)[1] = make_double2(Sv[2], Sv[3]);
+                    }
+                    if (net) {
+                        reinterpret_cast<double2 *>(net + p)[0] = make_double2(nv[0], nv[1]);
+                        reinterpret_cast<double2 *>(net + p)[1] = make_double2(nv[2], nv[3]);
+                    }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        if ((nib >> v) & 1u) {
+                            if (cum) cum[p + v] = Sv[v];
+                            if (net) net[p + v] = nv[v];
+                        }
+                    }
                 }
                 carry = shfl_acc(Acc<T>::combine(sbase, pre[3]), kWave - 1);
                 carry_net = __shfl(Av[3], kWave - 1);
