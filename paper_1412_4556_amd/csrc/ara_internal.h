@@ -50,8 +50,8 @@ struct TablesView {
     // set iff an event of block 32w+b (a block being 2^fshift consecutive
     // events) has a non-zero occurrence loss.  When fshift > 0 a second,
     // hashed filter follows in filt[n_fwords .. n_fwords + n_hwords): bit
-    // (E * kHashMul mod 2^32) >> hshift is set for every event E with a
-    // non-zero occurrence loss (n_hwords = 0: none).
+    // ((E mod 2^24) * kHashMul24 mod 2^32) >> hshift is set for every event E
+    // with a non-zero occurrence loss (n_hwords = 0: none).
     const void *occ;
     const uint32_t *filt;
     int32_t n_fwords;
@@ -65,9 +65,14 @@ struct TablesView {
 // Largest block filter the fused pass keeps in LDS (bits): 128 KiB.
 constexpr int64_t kFilterBits = 1 << 20;
 // LDS of the fused pass for both filters (bytes), and the multiplier of the
-// hashed filter (2^32 / golden ratio, odd).
+// hashed filter: odd and below 2^24, so that the hash is one full-rate
+// 24 x 24-bit multiply (IDs above 2^24 hash by their low 24 bits: more
+// collisions, never a missed event).  Its filters let through as few events
+// as a 32-bit multiplicative hash (checked on random, clustered and
+// paper-shaped key sets); the golden-ratio fraction 0x9E3779 does not (its
+// products' top bits vary slowly over IDs below 2^21: twice the false hits).
 constexpr int64_t kFusedLdsBytes = 160 * 1024;
-constexpr uint32_t kHashMul = 0x9E3779B1u;
+constexpr uint32_t kHashMul24 = 0xEBCA6Bu;
 
 enum Layout : int32_t {
     kDirect = ARA_LAYOUT_DIRECT,

@@ -92,6 +92,14 @@ struct EventSum<float> {
 // cross-lane moves
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
+// Bit of the hashed filter for an event ID: the top 32 - hshift bits of the
+// low 32 bits of a full-rate 24 x 24-bit product.  __umul24 returns a signed
+// int: the product is taken as unsigned before the shift, so the slot stays
+// below 2^(32 - hshift), the filter's size in bits.
+__device__ __forceinline__ uint32_t hash_slot(uint32_t id, int32_t hshift) {
+    return (uint32_t)__umul24(id, kHashMul24) >> hshift;
+}
+
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ int dpp_i(int v) {
     // lanes of rows outside ROW_MASK, and lanes whose source is outside the
@@ -510,7 +518,7 @@ __device__ __forceinline__ void gather_group(const IdGroupT<G> &g, uint32_t vali
             const uint32_t blk = (uint32_t)g.id[c][v] >> f.fshift;
             uint32_t hit = ((valid >> (4 * c + v)) & 1u) & __builtin_amdgcn_ubfe(sfilt[blk >> 5], blk, 1u);
             if (HASH) {
-                const uint32_t h = ((uint32_t)g.id[c][v] * kHashMul) >> f.hshift;
+                const uint32_t h = hash_slot((uint32_t)g.id[c][v], f.hshift);
                 hit &= __builtin_amdgcn_ubfe(shash[h >> 5], h, 1u);
             }
             idx[c][v] = hit ? g.id[c][v] : zero_slot;
@@ -1022,13 +1030,13 @@ __global__ void k_build_filter(const T *__restrict__ occ, int64_t catalog, int32
     }
 }
 
-// Hashed filter: bit (E * kHashMul) >> hshift for every event E with a
-// non-zero occurrence loss (words cleared beforehand).
+// Hashed filter: bit ((E mod 2^24) * kHashMul24) >> hshift for every event E
+// with a non-zero occurrence loss (words cleared beforehand).
 template <typename T>
 __global__ void k_hash_filter(const T *__restrict__ occ, int64_t catalog, int32_t hshift, uint32_t *__restrict__ words) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < catalog; e += (int64_t)gridDim.x * blockDim.x)
         if (occ[e] != T(0)) {
-            const uint32_t h = ((uint32_t)e * kHashMul) >> hshift;
+            const uint32_t h = hash_slot((uint32_t)e, hshift);
             atomicOr(&words[h >> 5], 1u << (h & 31u));
         }
 }
