@@ -87,9 +87,10 @@ class BatchingServer:
     """Continuous-batching server over one YET and one ELT pool.  Its streams
     and its two batch objects live as long as the server, so repeated runs
     pay no set-up; a group of fewer than ``min_batch`` queries runs as
-    back-to-back single-layer passes (the record pass costs about the same
-    for any number of layers, so below the crossover ``warm_up`` measures it
-    loses to separate passes)."""
+    back-to-back single-layer passes followed by one PML/TVaR call for the
+    group, all on the run stream, and is answered at once (the record pass
+    costs about the same for any number of layers, so below the crossover
+    ``warm_up`` measures it loses to separate passes)."""
 
     def __init__(self, yet: A.Yet, pool: A.Pool, return_periods=(100.0, 250.0), max_batch: int = L.ARA_MAX_BATCH,
                  min_batch: int = 2):
@@ -144,9 +145,24 @@ class BatchingServer:
                 with torch.cuda.stream(run_s):
                     outs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in group]
                     if len(group) < max(2, self.min_batch):
+                        # below the crossover: the group's passes and one
+                        # PML/TVaR call for all of them on the run stream,
+                        # answered at once (as one query at a time would be,
+                        # with the risk metrics of the group in one call)
                         for q, o in zip(group, outs):
                             A.run_layer(yet, q.layer, out=o, stream=run_s)
-                        slot = None
+                        pml, tvar = A.pml_tvar_many(outs, self.return_periods, stream=run_s)
+                        t = clock()
+                        for i, q in enumerate(group):
+                            q.done = t
+                            q.batch_size = len(group)
+                            q.pml, q.tvar = pml[i], tvar[i]
+                            q.ylt = outs[i] if keep_ylt else None
+                            q.layer.close()
+                            q.layer = None
+                        n_done += len(group)
+                        n_launches += 1
+                        continue
                     else:
                         slot = free_batch.pop()
                         layers = [q.layer for q in group]
