@@ -102,10 +102,10 @@ def cpu_baseline(wl, spec, target_s, gpu_ylt=None, gpu_pml_tvar=None, rps=()):
     threads = host_threads()
     J = spec.n_elts
 
-    def run(n):
+    def run(n, n_threads=threads):
         ids, off = W.yet_subset(wl.yet, np.arange(n))
         t = time.perf_counter()
-        r = oracle.run_layer(ids, off, n, 0, wl.yet.catalog_size, spec, n_threads=threads)
+        r = oracle.run_layer(ids, off, n, 0, wl.yet.catalog_size, spec, n_threads=n_threads)
         return time.perf_counter() - t, int(off[-1]), r
 
     probe = min(2000 * threads, wl.yet.n_trials)
@@ -116,6 +116,12 @@ def cpu_baseline(wl, spec, target_s, gpu_ylt=None, gpu_pml_tvar=None, rps=()):
            "sample": f"first {n} of {wl.yet.n_trials} trials ({ev} trial-events x {J} ELTs), FP64, "
                      f"OpenMP over trials, {dt:.1f} s incl. direct-table build",
            "cpu_model": cpu_model(), "seconds": dt}
+    # the same loop on one core (the paper's sequential form), on a smaller sample
+    n1 = int(min(wl.yet.n_trials, max(100, n / threads / 4)))
+    dt1, ev1, _ = run(n1, 1)
+    res["single_thread"] = {"value": ev1 * J / dt1, "unit": "lookups/s", "cores": 1,
+                            "sample": f"first {n1} trials ({ev1} trial-events x {J} ELTs), {dt1:.1f} s "
+                                      f"incl. direct-table build"}
     if gpu_ylt is not None:
         err = np.abs(gpu_ylt[:n] - ref["ylt"])
         scaled = err / np.maximum(ref["gross"], 1e-300)
