@@ -122,6 +122,17 @@ def cpu_baseline(wl, spec, target_s, gpu_ylt=None, gpu_pml_tvar=None, rps=()):
     res["single_thread"] = {"value": ev1 * J / dt1, "unit": "lookups/s", "cores": 1,
                             "sample": f"first {n1} trials ({ev1} trial-events x {J} ELTs), {dt1:.1f} s "
                                       f"incl. direct-table build"}
+    # and whole on the two small workloads (parity: 10k x 1000 events, 4 ELTs;
+    # precision: 10k Poisson(1000) trials, 4 ELTs of Pareto losses)
+    small = {}
+    for w in (W.plain_tiny(), W.precision_poisson()):
+        ids, off = W.yet_subset(w.yet, np.arange(w.yet.n_trials))
+        lay = w.layers[0]
+        t = time.perf_counter()
+        oracle.run_layer(ids, off, w.yet.n_trials, 0, w.yet.catalog_size, lay, n_threads=1)
+        dts = time.perf_counter() - t
+        small[w.name] = {"value": int(off[-1]) * lay.n_elts / dts, "unit": "lookups/s", "seconds": dts}
+    res["single_thread_small_workloads"] = small
     if gpu_ylt is not None:
         err = np.abs(gpu_ylt[:n] - ref["ylt"])
         scaled = err / np.maximum(ref["gross"], 1e-300)
