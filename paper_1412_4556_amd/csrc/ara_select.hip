@@ -324,7 +324,8 @@ __global__ __launch_bounds__(kSumBlocks) void k_tail_finish(const SelState *st, 
 // that the finishing kernels write the results into.  ara_pml_tvar is
 // synchronous and holds the device's lock for the duration of a call.  A
 // call that fails after its first launch marks the scratch dirty, and the
-// next call clears the histograms and the flag before it starts.
+// next call waits for the device, then clears the histograms and the flag
+// before it starts.
 struct Scratch {
     std::mutex mu;
     void *d = nullptr;
@@ -393,6 +394,8 @@ hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n
     const int n_sel = n_ylt * n_rp;
 
     if (sc.dirty) {
+        // the failed call's kernels may still run, on another stream
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
         if ((e = hipMemsetAsync(nan_flag, 0, 16, s)) != hipSuccess) return e;
         if ((e = hipMemsetAsync(hist, 0, off_psum - off_hist, s)) != hipSuccess) return e;
         sc.dirty = false;
