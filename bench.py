@@ -309,8 +309,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(trials would shard by range across GPUs; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (trials would shard by trial "
+              "range across GPUs, with one exchange of the local top-k for PML/TVaR)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
