@@ -48,7 +48,7 @@ typedef int32_t ara_status;
 #define ARA_ERR_OOM -5          /* device or host allocation failed; no state was changed */
 #define ARA_ERR_DEVICE -6       /* a HIP call failed */
 #define ARA_ERR_RP -7           /* a return period leaves no tail trial (floor(T/N) < 1) */
-#define ARA_ERR_UNSUPPORTED -8  /* a valid request this build does not handle (e.g. too many ELTs) */
+#define ARA_ERR_UNSUPPORTED -8  /* a valid request the library does not handle (e.g. too many ELTs) */
 
 #define ARA_MAX_ELTS 32         /* ELTs per layer; the paper's layers cover 3 to 30 */
 #define ARA_MAX_BATCH 64        /* layers per batch, YLTs per ara_pml_tvar_many call */

@@ -31,13 +31,15 @@
  *   of the trial (0 for an empty trial): the loss on an occurrence basis,
  *   from which occurrence-basis PML/TVaR and return period losses follow
  *   the same way as from the YLT (the paper names return period losses
- *   among the reports derived from the analysis, Section III; the
- *   occurrence basis is a reading, see the design notes).
+ *   among the reports derived from the analysis, Section III, without
+ *   naming their basis: taking the per-trial largest occurrence loss as the
+ *   occurrence basis is a reading).
  *
- * Readings of points the paper leaves open are listed in the design notes:
- * the max(., 0) missing an argument in the printed FT2/FT3 formulas, the
- * reset of the event loss per event, FT1 taken as a retention/limit pair
- * of the same form as FT2/FT3.
+ * Readings of points the paper leaves open: the printed FT2/FT3 formulas
+ * give max(.) a single argument, read as max(x - retention, 0); the event
+ * loss is reset for every event (the text applies the occurrence terms to
+ * each occurrence independently); FT1 is a retention/limit pair of the same
+ * form as FT2/FT3.
  *
  * Lookups use one dense direct-access table per ELT (catalogue-sized, zero
  * for absent events), as the paper's implementations do (Section IV, data
