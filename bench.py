@@ -327,7 +327,15 @@ def main():
     t_ids = torch.from_numpy(ids).cuda()
     del ids
     yet = A.Yet(t_ids, None, T, wl.yet.catalog_size, K)
+    # the layer's tables (for the fused layout: every event's occurrence loss
+    # and the LDS filters) are built once per layer, outside the timed step;
+    # the second build is the steady-state cost (the first one also loads code)
+    A.Layer(yet, spec, args.precision, args.layout).close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     lay = A.Layer(yet, spec, args.precision, args.layout)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
     ylt = torch.empty(T, dtype=torch.float64, device="cuda")
     rps = list(wl.return_periods)
     log(f"layer: {J} ELTs, layout {lay.layout}, precision {lay.precision}, {lay.device_bytes} device bytes")
@@ -436,6 +444,11 @@ def main():
                    "elts": J, "elt_size": 20_000, "layout": lay_layout, "precision": lay_prec,
                    "return_periods": rps},
         "trial_events_per_s": T * K / (ms_step * 1e-3),
+        "lookups_are": ("equivalent: the fused layout adds the J ELTs' losses of each catalogue event once per "
+                        "layer (layer_build_ms) and looks each trial-event up once"
+                        if lay_layout == "fused" else "J ELT lookups per trial-event"),
+        "layer_build_ms": build_ms,
+        "value_incl_layer_build": lookups / ((ms_step + build_ms) * 1e-3),
         "kernel_ms": k_ms,
         "hbm_gbps_algorithmic": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",

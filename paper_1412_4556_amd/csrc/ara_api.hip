@@ -269,6 +269,54 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
         h.tab.sp_ids = static_cast<const int32_t *>(d0);
         h.tab.sp_loss = d1;
         h.tab.sp_off = static_cast<const int64_t *>(d2);
+    } else if (h.layout == ara::kFused) {
+        // occurrence loss per catalogue event, built on the GPU from the
+        // layer's ELTs in layer order (the kernels of pool layers), then the
+        // LDS filters
+        const size_t n = (size_t)start[J];
+        const void *d_ids, *d_loss;
+        if ((st = upload(h, 0, ids, n, &d_ids)) != ARA_OK) return st;
+        if (sizeof(T) == sizeof(double)) {
+            if ((st = upload(h, 1, reinterpret_cast<const T *>(loss), n, &d_loss)) != ARA_OK) return st;
+        } else {
+            std::vector<T> lt(n);
+            for (size_t i = 0; i < n; ++i) lt[i] = (T)loss[i];
+            if ((st = upload(h, 1, lt.data(), n, &d_loss)) != ARA_OK) return st;
+        }
+        int32_t fshift = 0, n_fwords = 0, n_hwords = 0, hshift = 0;
+        filter_geometry((int32_t)C, fshift, n_fwords, n_hwords, hshift);
+        void *d_occ = nullptr, *d_filt = nullptr, *d_lo = nullptr;
+        // catalogue + 1 entries: occ[C] stays 0 for the pass's unmarked lanes
+        hipError_t e = dev_alloc(&d_occ, ((size_t)C + 1) * sizeof(T));
+        if (e != hipSuccess) return hip_fail(e, "device allocation of the fused table");
+        h.alloc[2] = d_occ;
+        h.bytes += ((size_t)C + 1) * sizeof(T);
+        e = dev_alloc(&d_filt, (size_t)(n_fwords + n_hwords) * sizeof(uint32_t));
+        if (e != hipSuccess) return hip_fail(e, "device allocation of the fused filter");
+        h.alloc[3] = d_filt;
+        h.bytes += (size_t)(n_fwords + n_hwords) * sizeof(uint32_t);
+        if (sizeof(T) == sizeof(float)) {  // compensation terms of the binary32 sums while building
+            e = dev_alloc(&d_lo, (size_t)C * sizeof(float));
+            if (e != hipSuccess) return hip_fail(e, "device allocation of the build scratch");
+            h.alloc[4] = d_lo;
+            h.bytes += (size_t)C * sizeof(float);
+        }
+        h.tab.occ = d_occ;
+        h.tab.filt = static_cast<const uint32_t *>(d_filt);
+        h.tab.fshift = fshift;
+        h.tab.n_fwords = (int32_t)n_fwords;
+        h.tab.n_hwords = n_hwords;
+        h.tab.hshift = hshift;
+        std::vector<int32_t> order(J);
+        for (int j = 0; j < J; ++j) order[j] = j;
+        hipStream_t s = ara::internal_stream();
+        e = ara::launch_pool_layer(h, static_cast<const int32_t *>(d_ids), d_loss, start.data(), order.data(), J,
+                                   static_cast<float *>(d_lo), s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "building the fused table");
+        release_slot(h, 0, n * sizeof(int32_t));
+        release_slot(h, 1, n * sizeof(T));
+        release_slot(h, 4, (size_t)C * sizeof(float));
     } else {
         const int64_t n_words = (C + 31) / 32;
         std::vector<uint2> bm((size_t)n_words, uint2{0u, 0u});
@@ -297,47 +345,12 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
                 size_t idx = (size_t)w.y + (size_t)__builtin_popcount(w.x & (bit - 1u));
                 rows[idx * J + j] = (T)loss[start[j] + n];
             }
-        if (h.layout == ara::kCompact) {
-            const void *d0, *d1;
-            if ((st = upload(h, 0, bm.data(), bm.size(), &d0)) != ARA_OK) return st;
-            if ((st = upload(h, 1, rows.data(), rows.size(), &d1)) != ARA_OK) return st;
-            h.tab.bm = static_cast<const uint2 *>(d0);
-            h.tab.rows = d1;
-            h.tab.n_words = (int32_t)n_words;
-        } else {
-            // fused: occurrence loss per catalogue event and the LDS filter
-            std::vector<int32_t> present;
-            present.reserve(rank);
-            for (int64_t w = 0; w < n_words; ++w)
-                for (uint32_t x = bm[w].x; x; x &= x - 1u) present.push_back((int32_t)(w * 32 + __builtin_ctz(x)));
-            int32_t fshift = 0, n_fwords = 0, n_hwords = 0, hshift = 0;
-            filter_geometry((int32_t)C, fshift, n_fwords, n_hwords, hshift);
-            const void *d_rows, *d_present;
-            if ((st = upload(h, 0, rows.data(), rows.size(), &d_rows)) != ARA_OK) return st;
-            if ((st = upload(h, 1, present.data(), present.size(), &d_present)) != ARA_OK) return st;
-            void *d_occ = nullptr, *d_filt = nullptr;
-            // catalogue + 1 entries: occ[C] stays 0 for the pass's unmarked lanes
-            hipError_t e = dev_alloc(&d_occ, ((size_t)C + 1) * sizeof(T));
-            if (e != hipSuccess) return hip_fail(e, "device allocation of the fused table");
-            h.alloc[2] = d_occ;
-            h.bytes += ((size_t)C + 1) * sizeof(T);
-            e = dev_alloc(&d_filt, (size_t)(n_fwords + n_hwords) * sizeof(uint32_t));
-            if (e != hipSuccess) return hip_fail(e, "device allocation of the fused filter");
-            h.alloc[3] = d_filt;
-            h.bytes += (size_t)(n_fwords + n_hwords) * sizeof(uint32_t);
-            h.tab.occ = d_occ;
-            h.tab.filt = static_cast<const uint32_t *>(d_filt);
-            h.tab.fshift = fshift;
-            h.tab.n_fwords = (int32_t)n_fwords;
-            h.tab.n_hwords = n_hwords;
-            h.tab.hshift = hshift;
-            hipStream_t s = ara::internal_stream();
-            e = ara::launch_fuse(h, d_rows, static_cast<const int32_t *>(d_present), (int64_t)rank, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return hip_fail(e, "building the fused table");
-            release_slot(h, 0, rows.size() * sizeof(T));
-            release_slot(h, 1, present.size() * sizeof(int32_t));
-        }
+        const void *d0, *d1;
+        if ((st = upload(h, 0, bm.data(), bm.size(), &d0)) != ARA_OK) return st;
+        if ((st = upload(h, 1, rows.data(), rows.size(), &d1)) != ARA_OK) return st;
+        h.tab.bm = static_cast<const uint2 *>(d0);
+        h.tab.rows = d1;
+        h.tab.n_words = (int32_t)n_words;
     }
     return ARA_OK;
 }

@@ -99,9 +99,6 @@ struct LayerHost {
 hipStream_t internal_stream();
 
 // Launchers (ara_kernels.hip).  Return a hipError_t.
-// Fused tables: occ[] from the compact rows (rows[n_present][n_elts],
-// present_ids[n_present]), then the LDS filter bits.
-hipError_t launch_fuse(LayerHost &L, const void *d_rows, const int32_t *d_present, int64_t n_present, hipStream_t s);
 hipError_t launch_validate_yet(const YetView &y, int32_t catalog, int32_t *d_flags, hipStream_t s);
 // d_omax (optional, [n_trials]): the largest occurrence loss of each trial.
 hipError_t launch_trial_pass(const YetView &y, const LayerHost &L, double *d_ylt, double *d_omax, hipStream_t s);
@@ -150,8 +147,11 @@ hipError_t launch_batch_fill(const void *const *occ, int32_t n_layers, int32_t c
                              unsigned long long *d_ovf_cursor, hipStream_t s);
 hipError_t launch_batch_pass(const YetView &y, const BatchTables &b, bool fp64, const BatchLaunch &cfg, hipStream_t s);
 size_t batch_lds_bytes(int32_t n_layers, int threads);
-// Fused table of a layer from pool ELTs idx[0..n) (host offsets off[]),
-// enqueued on s; d_lo: binary32 scratch [catalog] for FP32C, else unused.
+// Fused table of a layer, built on the GPU: the ELTs idx[0..n) of device
+// arrays d_ids / d_loss (ELT k at host offsets off[k] .. off[k + 1]) added
+// in that order, then the occurrence terms and the LDS filters; enqueued on
+// s.  Used for pool layers and for layers from host ELTs alike.  d_lo:
+// binary32 scratch [catalog] for FP32C, else unused.
 hipError_t launch_pool_layer(LayerHost &L, const int32_t *d_ids, const void *d_loss, const int64_t *h_off,
                              const int32_t *h_idx, int32_t n, float *d_lo, hipStream_t s);
 // d[0 .. n) = 0 with a kernel (no memset node if the caller captures a graph)

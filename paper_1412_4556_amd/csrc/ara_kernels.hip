@@ -997,20 +997,6 @@ __global__ void k_fill_zero(T *p, int64_t n) {
         p[i] = T(0);
 }
 
-// occ[E] for every event present in some ELT: the same arithmetic, in the
-// same order, as the per-event lookup of the compact layout.
-template <typename T>
-__global__ void k_fuse(const T *__restrict__ rows, const int32_t *__restrict__ present, int64_t n_present, Terms<T> t,
-                       T *__restrict__ occ) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_present;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const T *row = rows + i * t.n_elts;
-        EventSum<T> s;
-        for (int j = 0; j < t.n_elts; ++j) s.add(clamp_excess(row[j], t.ret[j], t.lim[j]));
-        occ[present[i]] = clamp_excess(s.value(), t.occ_ret, t.occ_lim);
-    }
-}
-
 template <typename T>
 __global__ void k_build_filter(const T *__restrict__ occ, int64_t catalog, int32_t fshift, uint32_t *__restrict__ filt,
                                int32_t n_fwords) {
@@ -1204,32 +1190,6 @@ hipStream_t internal_stream() {
         streams[dev] = st;
     }
     return streams[dev];
-}
-
-namespace {
-template <typename T>
-hipError_t fuse_t(LayerHost &L, const Terms<T> &t, const void *d_rows, const int32_t *d_present, int64_t n_present,
-                  hipStream_t s) {
-    T *occ = static_cast<T *>(const_cast<void *>(L.tab.occ));
-    const int g = cu_count() * 4;
-    hipLaunchKernelGGL((k_fill_zero<T>), dim3(g), dim3(256), 0, s, occ, (int64_t)L.catalog + 1);
-    if (n_present > 0)
-        hipLaunchKernelGGL((k_fuse<T>), dim3(g), dim3(256), 0, s, static_cast<const T *>(d_rows), d_present, n_present,
-                           t, occ);
-    hipLaunchKernelGGL((k_build_filter<T>), dim3(g), dim3(256), 0, s, occ, (int64_t)L.catalog, L.tab.fshift,
-                       const_cast<uint32_t *>(L.tab.filt), L.tab.n_fwords);
-    if (L.tab.n_hwords > 0) {
-        uint32_t *hw = const_cast<uint32_t *>(L.tab.filt) + L.tab.n_fwords;
-        hipLaunchKernelGGL((k_fill_zero<uint32_t>), dim3(g), dim3(256), 0, s, hw, (int64_t)L.tab.n_hwords);
-        hipLaunchKernelGGL((k_hash_filter<T>), dim3(g), dim3(256), 0, s, occ, (int64_t)L.catalog, L.tab.hshift, hw);
-    }
-    return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_fuse(LayerHost &L, const void *d_rows, const int32_t *d_present, int64_t n_present, hipStream_t s) {
-    if (L.precision == ARA_FP32C) return fuse_t<float>(L, L.t32, d_rows, d_present, n_present, s);
-    return fuse_t<double>(L, L.t64, d_rows, d_present, n_present, s);
 }
 
 hipError_t launch_validate_yet(const YetView &y, int32_t catalog, int32_t *d_flags, hipStream_t s) {
