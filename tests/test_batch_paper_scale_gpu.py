@@ -4,7 +4,8 @@
 Every batched YLT is bitwise the single-layer pass of its layer over the
 whole YET; the oracle recomputes a sample of trials of every layer,
 regenerated on the host from the same seeded blocks; the risk metrics of the
-full YLTs agree with the oracle's selection."""
+full YLTs agree with the oracle's selection, and their roll-up into programs
+and a portfolio is bitwise the oracle's."""
 import numpy as np
 import pytest
 import torch
@@ -67,6 +68,18 @@ def test_batch_paper_scale(batch_paper, prec):
         assert np.array_equal(gp[r], op), i
         assert np.allclose(gt[r], ot, rtol=1e-12, atol=0), i
     assert sum(int((o > 0).sum()) for o in outs) > 0
+    # roll-up as the benchmark times it: programs of 8 consecutive layers,
+    # then the portfolio of the programs, bitwise the oracle's
+    groups = [l * 8 // len(outs) for l in range(len(outs))]
+    progs = A.rollup(outs, groups, 8)
+    pfolio = A.rollup(progs, [0] * 8, 1)
+    torch.cuda.synchronize()
+    host = [o.cpu().numpy() for o in outs]
+    ref_p = oracle.rollup(host, groups, 8)
+    ref_f = oracle.rollup(ref_p, [0] * 8, 1)
+    for g in range(8):
+        assert np.array_equal(progs[g].cpu().numpy(), ref_p[g]), g
+    assert np.array_equal(pfolio[0].cpu().numpy(), ref_f[0])
     b.close()
     for lay in layers:
         lay.close()
