@@ -95,8 +95,15 @@ struct LayerHost {
     void *alloc[6] = {};
 };
 
-// A non-blocking stream of the library for its own set-up work (one per device).
+// A non-blocking stream of the library for its own set-up work (one per
+// device, created on first use; safe to call from several host threads).
 hipStream_t internal_stream();
+// Compute units of the current device (cached per device; 256 if unknown).
+constexpr int kMaxDevices = 64;
+int cu_count();
+// Raises the dynamic LDS limit of a kernel to bytes on the current device,
+// once per (device, kernel, bytes); safe to call from several host threads.
+hipError_t allow_dynamic_lds(const void *kern, int bytes);
 
 // Launchers (ara_kernels.hip).  Return a hipError_t.
 hipError_t launch_validate_yet(const YetView &y, int32_t catalog, int32_t *d_flags, hipStream_t s);

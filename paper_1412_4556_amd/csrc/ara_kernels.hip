@@ -13,6 +13,12 @@
 // which yields the cumulative loss S_k after every event.
 #include "ara_internal.h"
 
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <set>
+#include <tuple>
+
 namespace ara {
 namespace {
 
@@ -1072,19 +1078,6 @@ __global__ __launch_bounds__(256) void k_validate_yet(const int32_t *__restrict_
 }
 
 // --------------------------------------------------------------------------------------------
-int cu_count() {
-    static int cached[64] = {0};
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    if (dev < 0 || dev >= 64) dev = 0;
-    if (!cached[dev]) {
-        int n = 0;
-        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-        cached[dev] = n;
-    }
-    return cached[dev];
-}
-
 int grid_for_trials(int64_t n_trials, int waves_per_block, int blocks_per_cu) {
     int64_t need = (n_trials + waves_per_block - 1) / waves_per_block;
     int64_t cap = (int64_t)cu_count() * blocks_per_cu;
@@ -1132,13 +1125,8 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
                                nullptr,
                                nullptr};
         const void *kern = events ? reinterpret_cast<const void *>(ek[variant]) : reinterpret_cast<const void *>(pk[pv]);
-        static bool attr_set[2][2][16] = {};
-        bool &done = attr_set[sizeof(T) == 8 ? 0 : 1][events ? 1 : 0][events ? variant : pv];
-        if (!done) {
-            hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsBytes);
-            if (e != hipSuccess) return e;
-            done = true;
-        }
+        hipError_t ae = allow_dynamic_lds(kern, (int)kFusedLdsBytes);
+        if (ae != hipSuccess) return ae;
         const int per_cu = lds > (size_t)kFusedLdsBytes / 2 ? 1 : 2;
         const int fgrid = grid_for_trials(y.n_trials, 16, per_cu);
         const T *occ = static_cast<const T *>(L.tab.occ);
@@ -1179,17 +1167,48 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
 
 }  // namespace
 
-hipStream_t internal_stream() {
-    static hipStream_t streams[64] = {};
+int cu_count() {
+    static std::atomic<int> cached[kMaxDevices];
     int dev = 0;
-    (void)hipGetDevice(&dev);
-    dev &= 63;
-    if (!streams[dev]) {
-        hipStream_t st = nullptr;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
-        streams[dev] = st;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    const bool cacheable = dev >= 0 && dev < kMaxDevices;
+    if (cacheable) {
+        const int c = cached[dev].load(std::memory_order_relaxed);
+        if (c > 0) return c;
     }
-    return streams[dev];
+    int n = 0;
+    if (dev < 0 || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+        n = 256;
+    if (cacheable) cached[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
+
+hipError_t allow_dynamic_lds(const void *kern, int bytes) {
+    static std::mutex mu;
+    static std::set<std::tuple<int, const void *, int>> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const auto key = std::make_tuple(dev, kern, bytes);
+    std::lock_guard<std::mutex> g(mu);
+    if (done.count(key)) return hipSuccess;
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) done.insert(key);
+    return e;
+}
+
+hipStream_t internal_stream() {
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams[dev] = st;
+    return st;
 }
 
 hipError_t launch_validate_yet(const YetView &y, int32_t catalog, int32_t *d_flags, hipStream_t s) {
@@ -1236,14 +1255,8 @@ hipError_t batch_pass_t(const YetView &y, const BatchTables &b, const BatchLaunc
                       : (y.aligned16 ? &k_trial_pass_batch<T, false, true> : &k_trial_pass_batch<T, false, false>);
     const size_t lds = batch_lds_bytes(b.n_layers, cfg.threads);
     if (lds > 160u * 1024u || cfg.threads < kWave || cfg.threads > 512 || cfg.threads % kWave) return hipErrorInvalidValue;
-    static bool attr_set[2][3] = {};
-    bool &done = attr_set[sizeof(T) == 8 ? 0 : 1][fixed ? 0 : (y.aligned16 ? 1 : 2)];
-    if (!done) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        done = true;
-    }
+    hipError_t ae = allow_dynamic_lds(reinterpret_cast<const void *>(kern), 160 * 1024);
+    if (ae != hipSuccess) return ae;
     int per_cu = (int)((160 * 1024) / (lds ? lds : 1));
     if (per_cu > cfg.wg_per_cu) per_cu = cfg.wg_per_cu;
     if (per_cu < 1) per_cu = 1;

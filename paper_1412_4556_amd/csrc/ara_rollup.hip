@@ -11,19 +11,6 @@
 namespace ara {
 namespace {
 
-int rollup_cu_count() {
-    static int cached[64] = {0};
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    if (dev < 0 || dev >= 64) dev = 0;
-    if (!cached[dev]) {
-        int n = 0;
-        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-        cached[dev] = n;
-    }
-    return cached[dev];
-}
-
 __global__ __launch_bounds__(256) void k_rollup(RollupTables a, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -40,7 +27,7 @@ __global__ __launch_bounds__(256) void k_rollup(RollupTables a, int64_t n) {
 hipError_t launch_rollup(const RollupTables &a, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
-    const int64_t cap = (int64_t)rollup_cu_count() * 16;
+    const int64_t cap = (int64_t)cu_count() * 16;
     if (blocks > cap) blocks = cap;
     hipLaunchKernelGGL(k_rollup, dim3((unsigned)blocks), dim3(256), 0, s, a, n);
     return hipGetLastError();

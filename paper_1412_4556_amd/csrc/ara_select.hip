@@ -334,9 +334,10 @@ struct Scratch {
     bool dirty = false;
 };
 
+// dev in 0 .. kMaxDevices - 1 (checked by the caller)
 Scratch &scratch_for(int dev) {
-    static Scratch s[64];
-    return s[dev & 63];
+    static Scratch s[kMaxDevices];
+    return s[dev];
 }
 
 }  // namespace
@@ -347,6 +348,7 @@ hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     Scratch &sc = scratch_for(dev);
     std::lock_guard<std::mutex> g(sc.mu);
     // device layout: nan flag (16 B) | states per pass | histograms per pass | psum | pcnt
