@@ -27,6 +27,11 @@
  *   - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
  *     Launches are asynchronous on that stream unless stated otherwise.
  *   - All floating-point outputs are IEEE binary64.
+ *   - Host threads: calls may come from several threads at once, with two
+ *     exceptions: a batch handle is used by one thread at a time, and no
+ *     handle is destroyed while another call still uses it.  The library's
+ *     per-device state (launch attributes, its set-up stream, the PML/TVaR
+ *     scratch, whose calls on one device run one after another) is guarded.
  */
 #ifndef ARA_H
 #define ARA_H
