@@ -603,12 +603,19 @@ __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int6
         accumulate_group(o, acc);
         T m = T(0);
         if (OMAX) max_group(o, m);
-        for (int64_t base = chunk_start(y, r.b) + kSpan; base < r.e; base += kSpan) {
-            IdGroupT<G> more;
-            const uint32_t mv = load_group<FIXED, ALIGNED, G>(y, r, base, lane, last_granule, more);
-            gather_group<T, HASH, G>(more, mv, sfilt, f, zero_slot, occ, o);
-            accumulate_group(o, acc);
-            if (OMAX) max_group(o, m);
+        // the rest of a longer trial: whole groups for fixed-length trials,
+        // single chunks for variable-length ones (a Poisson(1000) trial
+        // exceeds a group by less than a chunk or two; a second group of
+        // registers would also cost occupancy-relevant VGPRs); each lane
+        // still adds its chunks in increasing order
+        constexpr int TG = FIXED ? G : 1;
+        for (int64_t base = chunk_start(y, r.b) + kSpan; base < r.e; base += (int64_t)TG * 4 * kWave) {
+            IdGroupT<TG> more;
+            const uint32_t mv = load_group<FIXED, ALIGNED, TG>(y, r, base, lane, last_granule, more);
+            T ot[TG][4];
+            gather_group<T, HASH, TG>(more, mv, sfilt, f, zero_slot, occ, ot);
+            accumulate_group<T, TG>(ot, acc);
+            if (OMAX) max_group<T, TG>(ot, m);
         }
         const double S = wave_allreduce(acc).value();
         if (lane == 0) ylt[trial] = clamp_excess(S, agg_ret, agg_lim);
@@ -1097,33 +1104,25 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
         if (lds > (size_t)kFusedLdsBytes) return hipErrorInvalidValue;
         const bool fixed = y.offsets == nullptr && y.aligned16 && y.events_per_trial > 0 && (y.events_per_trial % 4) == 0;
         const bool hash = f.n_hwords > 0;
-        // ragged aligned YETs of long trials take five-chunk groups (1,280
-        // events) in the YLT pass, so a Poisson(1000) trial rarely needs a
-        // second group (the per-event pass has no registers to spare for it)
-        const bool wide = !events && !fixed && y.aligned16 && y.n_trials > 0 && y.n_events / y.n_trials > 768;
-        const int variant = wide ? (hash ? 7 : 6) : (fixed ? 0 : (y.aligned16 ? 1 : 2)) + (hash ? 3 : 0);
+        const int variant = (fixed ? 0 : (y.aligned16 ? 1 : 2)) + (hash ? 3 : 0);
         using PassK = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const T *, double, double, double *,
                                double *);
         using EventsK = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const T *, double, double, double *,
                                  double *, double *);
-        const PassK pk[16] = {
+        const PassK pk[12] = {
             &k_trial_pass_fused<T, true, true, false, 4, false>,  &k_trial_pass_fused<T, false, true, false, 4, false>,
             &k_trial_pass_fused<T, false, false, false, 4, false>, &k_trial_pass_fused<T, true, true, true, 4, false>,
             &k_trial_pass_fused<T, false, true, true, 4, false>,  &k_trial_pass_fused<T, false, false, true, 4, false>,
-            &k_trial_pass_fused<T, false, true, false, 5, false>, &k_trial_pass_fused<T, false, true, true, 5, false>,
             &k_trial_pass_fused<T, true, true, false, 4, true>,   &k_trial_pass_fused<T, false, true, false, 4, true>,
             &k_trial_pass_fused<T, false, false, false, 4, true>, &k_trial_pass_fused<T, true, true, true, 4, true>,
-            &k_trial_pass_fused<T, false, true, true, 4, true>,   &k_trial_pass_fused<T, false, false, true, 4, true>,
-            &k_trial_pass_fused<T, false, true, false, 5, true>,  &k_trial_pass_fused<T, false, true, true, 5, true>};
-        const int pv = variant + (d_omax ? 8 : 0);
-        const EventsK ek[8] = {&k_trial_pass_events_fused<T, true, true, false, 4>,
+            &k_trial_pass_fused<T, false, true, true, 4, true>,   &k_trial_pass_fused<T, false, false, true, 4, true>};
+        const int pv = variant + (d_omax ? 6 : 0);
+        const EventsK ek[6] = {&k_trial_pass_events_fused<T, true, true, false, 4>,
                                &k_trial_pass_events_fused<T, false, true, false, 4>,
                                &k_trial_pass_events_fused<T, false, false, false, 4>,
                                &k_trial_pass_events_fused<T, true, true, true, 4>,
                                &k_trial_pass_events_fused<T, false, true, true, 4>,
-                               &k_trial_pass_events_fused<T, false, false, true, 4>,
-                               nullptr,
-                               nullptr};
+                               &k_trial_pass_events_fused<T, false, false, true, 4>};
         const void *kern = events ? reinterpret_cast<const void *>(ek[variant]) : reinterpret_cast<const void *>(pk[pv]);
         hipError_t ae = allow_dynamic_lds(kern, (int)kFusedLdsBytes);
         if (ae != hipSuccess) return ae;
