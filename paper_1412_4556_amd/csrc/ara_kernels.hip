@@ -927,6 +927,9 @@ __global__ __launch_bounds__(512) void k_trial_pass_batch(YetView y, const int64
         while (true) {
 #pragma unroll
             for (int c = 0; c < kGroup; ++c) {
+                // chunks that start past the trial's end hold no event (a
+                // variable-length trial's last group is mostly such padding)
+                if (c > 0 && base + (int64_t)c * 4 * kWave >= r.e) break;
                 OvHeads<T> oh;
                 load_ov_heads(rr[c & 1], (valid >> (4 * c)) & 0xfu, b, oh);
                 if (c + 1 < kGroup) {
