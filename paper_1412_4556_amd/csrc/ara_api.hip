@@ -2,6 +2,7 @@
 // errors.  The operations themselves run in the HIP kernels of
 // ara_kernels.hip and ara_select.hip.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -105,7 +106,21 @@ long long fault_budget() {
     }();
     return v;
 }
-long long g_alloc_count = 0;
+std::atomic<long long> g_alloc_count{0};
+
+// Device staging of the ELTs of fused layers built from host memory: one
+// buffer per device, grown on demand and kept until the process ends, used
+// under its lock (a build is synchronous).
+struct Staging {
+    std::mutex mu;
+    void *d = nullptr;
+    size_t cap = 0;
+};
+// dev in 0 .. kMaxDevices - 1 (checked by the caller)
+Staging &staging_for(int dev) {
+    static Staging s[ara::kMaxDevices];
+    return s[dev];
+}
 
 hipError_t dev_alloc(void **p, size_t bytes) {
     long long fb = fault_budget();
@@ -142,14 +157,6 @@ ara_status upload(ara::LayerHost &h, int slot, const T *src, size_t count, const
     return ARA_OK;
 }
 
-void release_slot(ara::LayerHost &h, int slot, size_t bytes) {
-    if (h.alloc[slot]) {
-        (void)hipFree(h.alloc[slot]);
-        h.alloc[slot] = nullptr;
-        h.bytes -= bytes;
-    }
-}
-
 ara_status validate_elts(int32_t C, int32_t n_elts, const int32_t *h_elt_ids, const double *h_elt_losses,
                          const int64_t *h_elt_sizes, std::vector<int64_t> &start) {
     start.assign(n_elts + 1, 0);
@@ -159,20 +166,25 @@ ara_status validate_elts(int32_t C, int32_t n_elts, const int32_t *h_elt_ids, co
         start[j + 1] = start[j] + h_elt_sizes[j];
     }
     if (start[n_elts] > 0 && (!h_elt_ids || !h_elt_losses)) return fail(ARA_ERR_INVALID_ARG, "NULL ELT arrays");
-    std::vector<int32_t> stamp;
+    // one bit per catalogue event (C / 8 bytes, cache-resident at the paper's
+    // sizes), set by an ELT's IDs and cleared again before the next ELT
+    std::vector<uint64_t> seen;
     try {
-        stamp.assign((size_t)C, 0);
+        seen.assign(((size_t)C + 63) / 64, 0);
     } catch (const std::bad_alloc &) {
         return fail(ARA_ERR_OOM, "host allocation");
     }
-    for (int j = 0; j < n_elts; ++j)
+    for (int j = 0; j < n_elts; ++j) {
         for (int64_t n = start[j]; n < start[j + 1]; ++n) {
             const int32_t e = h_elt_ids[n];
             if (e < 0 || e >= C) return fail(ARA_ERR_EVENT_RANGE, "ELT event ID outside [0, catalog_size)");
-            if (stamp[e] == j + 1) return fail(ARA_ERR_DUP_EVENT, "duplicate event ID in one ELT");
-            stamp[e] = j + 1;
+            const uint64_t bit = 1ULL << (e & 63);
+            if (seen[(size_t)e >> 6] & bit) return fail(ARA_ERR_DUP_EVENT, "duplicate event ID in one ELT");
+            seen[(size_t)e >> 6] |= bit;
             if (!finite_nonneg(h_elt_losses[n])) return fail(ARA_ERR_VALUE, "ELT loss must be finite and >= 0");
         }
+        for (int64_t n = start[j]; n < start[j + 1]; ++n) seen[(size_t)h_elt_ids[n] >> 6] = 0;
+    }
     return ARA_OK;
 }
 
@@ -272,22 +284,18 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
     } else if (h.layout == ara::kFused) {
         // occurrence loss per catalogue event, built on the GPU from the
         // layer's ELTs in layer order (the kernels of pool layers), then the
-        // LDS filters
+        // LDS filters; the ELTs are staged in the device's build buffer, so
+        // the build allocates nothing but the layer's own tables
         const size_t n = (size_t)start[J];
-        const void *d_ids, *d_loss;
-        if ((st = upload(h, 0, ids, n, &d_ids)) != ARA_OK) return st;
-        if (sizeof(T) == sizeof(double)) {
-            if ((st = upload(h, 1, reinterpret_cast<const T *>(loss), n, &d_loss)) != ARA_OK) return st;
-        } else {
-            std::vector<T> lt(n);
-            for (size_t i = 0; i < n; ++i) lt[i] = (T)loss[i];
-            if ((st = upload(h, 1, lt.data(), n, &d_loss)) != ARA_OK) return st;
-        }
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_fail(e, "current device");
+        if (dev < 0 || dev >= ara::kMaxDevices) return fail(ARA_ERR_UNSUPPORTED, "device id beyond the library's tables");
         int32_t fshift = 0, n_fwords = 0, n_hwords = 0, hshift = 0;
         filter_geometry((int32_t)C, fshift, n_fwords, n_hwords, hshift);
-        void *d_occ = nullptr, *d_filt = nullptr, *d_lo = nullptr;
+        void *d_occ = nullptr, *d_filt = nullptr;
         // catalogue + 1 entries: occ[C] stays 0 for the pass's unmarked lanes
-        hipError_t e = dev_alloc(&d_occ, ((size_t)C + 1) * sizeof(T));
+        e = dev_alloc(&d_occ, ((size_t)C + 1) * sizeof(T));
         if (e != hipSuccess) return hip_fail(e, "device allocation of the fused table");
         h.alloc[2] = d_occ;
         h.bytes += ((size_t)C + 1) * sizeof(T);
@@ -295,28 +303,53 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
         if (e != hipSuccess) return hip_fail(e, "device allocation of the fused filter");
         h.alloc[3] = d_filt;
         h.bytes += (size_t)(n_fwords + n_hwords) * sizeof(uint32_t);
-        if (sizeof(T) == sizeof(float)) {  // compensation terms of the binary32 sums while building
-            e = dev_alloc(&d_lo, (size_t)C * sizeof(float));
-            if (e != hipSuccess) return hip_fail(e, "device allocation of the build scratch");
-            h.alloc[4] = d_lo;
-            h.bytes += (size_t)C * sizeof(float);
-        }
         h.tab.occ = d_occ;
         h.tab.filt = static_cast<const uint32_t *>(d_filt);
         h.tab.fshift = fshift;
         h.tab.n_fwords = (int32_t)n_fwords;
         h.tab.n_hwords = n_hwords;
         h.tab.hshift = hshift;
+        // staging: IDs, losses in the layer's arithmetic and, for FP32C, the
+        // compensation terms of the binary32 sums (256-byte aligned parts)
+        const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t b_ids = up(n * sizeof(int32_t)), b_loss = up(n * sizeof(T));
+        const size_t b_lo = sizeof(T) == sizeof(float) ? up((size_t)C * sizeof(float)) : 0;
+        const size_t need = b_ids + b_loss + b_lo > 256 ? b_ids + b_loss + b_lo : 256;
+        std::vector<T> lt;
+        if (sizeof(T) != sizeof(double)) {
+            lt.resize(n);
+            for (size_t i = 0; i < n; ++i) lt[i] = (T)loss[i];
+        }
+        const void *h_loss = sizeof(T) == sizeof(double) ? static_cast<const void *>(loss) : lt.data();
+        Staging &sg = staging_for(dev);
+        std::lock_guard<std::mutex> g(sg.mu);
+        if (sg.cap < need) {
+            if (sg.d) (void)hipFree(sg.d);
+            sg.d = nullptr;
+            sg.cap = 0;
+            e = dev_alloc(&sg.d, need);
+            if (e != hipSuccess) {
+                sg.d = nullptr;
+                return hip_fail(e, "device allocation of the build staging");
+            }
+            sg.cap = need;
+        }
+        char *base = static_cast<char *>(sg.d);
+        int32_t *d_ids = reinterpret_cast<int32_t *>(base);
+        void *d_loss = base + b_ids;
+        float *d_lo = b_lo ? reinterpret_cast<float *>(base + b_ids + b_loss) : nullptr;
+        hipStream_t s = ara::internal_stream();
+        if (!s) return fail(ARA_ERR_DEVICE, "no set-up stream");
+        if (n) e = hipMemcpyAsync(d_ids, ids, n * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && n) e = hipMemcpyAsync(d_loss, h_loss, n * sizeof(T), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "copy of the layer's ELTs");
         std::vector<int32_t> order(J);
         for (int j = 0; j < J; ++j) order[j] = j;
-        hipStream_t s = ara::internal_stream();
-        e = ara::launch_pool_layer(h, static_cast<const int32_t *>(d_ids), d_loss, start.data(), order.data(), J,
-                                   static_cast<float *>(d_lo), s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        e = ara::launch_pool_layer(h, d_ids, d_loss, start.data(), order.data(), J, d_lo, s);
+        // the staging is reused by the next build only after this wait
+        const hipError_t se = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = se;
         if (e != hipSuccess) return hip_fail(e, "building the fused table");
-        release_slot(h, 0, n * sizeof(int32_t));
-        release_slot(h, 1, n * sizeof(T));
-        release_slot(h, 4, (size_t)C * sizeof(float));
     } else {
         const int64_t n_words = (C + 31) / 32;
         std::vector<uint2> bm((size_t)n_words, uint2{0u, 0u});

@@ -395,6 +395,16 @@ def test_create_errors():
     with pytest.raises(L.AraError) as ei:
         A.Layer(yet, one([1, 1], [1.0, 2.0]))
     assert ei.value.name == "ARA_ERR_DUP_EVENT"
+    # an event may sit in several ELTs of a layer; a duplicate inside a later
+    # ELT is still found (every ID here shares one 64-bit word of the check)
+    two = lambda a, b: W.LayerSpec([np.array(a, np.int32), np.array(b, np.int32)],
+                                   [np.ones(len(a)), np.ones(len(b))], np.zeros(2), np.full(2, np.inf), 0.0, np.inf,
+                                   0.0, np.inf)
+    for layout in ("fused", "compact", "direct", "sparse"):
+        A.Layer(yet, two([1, 2, 3], [3, 2, 1]), "fp64", layout).close()
+        with pytest.raises(L.AraError) as ei:
+            A.Layer(yet, two([1, 2], [3, 4, 3]), "fp64", layout)
+        assert ei.value.name == "ARA_ERR_DUP_EVENT", layout
     with pytest.raises(L.AraError) as ei:
         A.Layer(yet, one([1, 11], [1.0, 2.0]))
     assert ei.value.name == "ARA_ERR_EVENT_RANGE"
