@@ -128,7 +128,10 @@ ara_status ara_create_yet(const int32_t *d_event_ids, const int64_t *d_offsets, 
  *   agg_ret/agg_lim FT3 aggregate retention (finite, >= 0) / limit (>= 0 or +INF).
  *   precision       ara_precision; layout: ara_layout.
  * All host inputs are COPIED; the caller may free them on return.  Device
- * memory is owned by the layer until ara_destroy_layer.  Synchronous.
+ * memory is owned by the layer until ara_destroy_layer.  The FUSED layout
+ * stages the ELTs in a device buffer of the library (one per device, grown
+ * to the largest layer's ELT bytes, plus 4 bytes per catalogue event for
+ * FP32C, and kept until the process ends).  Synchronous.
  * Errors: ARA_ERR_INVALID_ARG, ARA_ERR_EVENT_RANGE, ARA_ERR_DUP_EVENT,
  * ARA_ERR_VALUE, ARA_ERR_UNSUPPORTED (n_elts > ARA_MAX_ELTS), ARA_ERR_OOM. */
 ara_status ara_create_layer(ara_yet yet, int32_t n_elts, const int32_t *h_elt_ids, const double *h_elt_losses,
