@@ -197,9 +197,15 @@ ara_status ara_create_batch(ara_yet yet, const ara_layer *layers, int32_t n_laye
 ara_status ara_run_batch(ara_batch batch, double *const *d_ylts, void *hip_stream);
 size_t ara_batch_device_bytes(ara_batch batch);
 /* Rebuild a batch's records for other layers (same YET and precision),
- * reusing its device memory.  Synchronous.  Once rebuilt with another number
- * of layers, the batch launches its pass directly instead of replaying a
- * captured graph (a server's batches change size all the time). */
+ * reusing its device memory (the overflow area grows when the new layers
+ * need more entries).  Synchronous.  It first waits for the batch's last
+ * ara_run_batch, on whatever stream that run was queued, so the caller need
+ * not synchronise before it.  A captured graph is replayed only while the
+ * tables it was captured with are unchanged (it is captured again after a
+ * rebuild that moved them); once rebuilt with another number of layers, the
+ * batch launches its pass directly instead (a server's batches change size
+ * all the time).  A run queued on another stream than the batch's previous
+ * run waits for that run. */
 ara_status ara_batch_rebuild(ara_batch batch, const ara_layer *layers, int32_t n_layers);
 /* Launch shape chosen for the batch (0, 0 before its first run). */
 ara_status ara_batch_launch_config(ara_batch batch, int32_t *threads, int32_t *wg_per_cu);

@@ -76,6 +76,16 @@ struct ara_batch_s {
     bool use_graph = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // what the captured graph's kernel arguments hold: it is replayed only
+    // while the batch's tables and launch shape are still these
+    ara::BatchTables graph_tables{};
+    ara::BatchLaunch graph_cfg{0, 0};
+    // recorded on the caller's stream after every run: a rebuild, and a run
+    // on another stream, wait for it before they overwrite what the last
+    // run reads (records, overflow entries, terms, YLT pointers)
+    hipEvent_t last_run = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool ran = false;
     size_t bytes = 0;
     int device = 0;
 };
@@ -719,9 +729,16 @@ ara_status ara_create_layer_from_pool(ara_pool pool, int32_t n_elts, const int32
     return ARA_OK;
 }
 
-static void free_batch(ara_batch b) {
+static void drop_graph(ara_batch b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+static void free_batch(ara_batch b) {
+    drop_graph(b);
+    if (b->last_run) (void)hipEventDestroy(b->last_run);
     for (void *p : {b->d_rec, b->d_ovf_lid, b->d_ovf_val, (void *)b->d_ylts, (void *)b->d_agg, (void *)b->d_count,
                      (void *)b->d_ctr})
         if (p) (void)hipFree(p);
@@ -754,7 +771,10 @@ ara_status ara_batch_rebuild(ara_batch b, const ara_layer *layers, int32_t n_lay
     const bool fp64 = prec == ARA_FP64;
     const size_t val_bytes = fp64 ? 8 : 4;
     hipStream_t s = ara::internal_stream();
+    if (!s) return fail(ARA_ERR_DEVICE, "no set-up stream");
     hipError_t e = hipSuccess;
+    // everything below overwrites what the batch's last run reads: wait for it
+    if (b->ran) e = hipStreamWaitEvent(s, b->last_run, 0);
     for (int l = 0; l < n_layers && e == hipSuccess; ++l)
         if (layers[l]->ready) e = hipStreamWaitEvent(s, layers[l]->ready, 0);
     unsigned long long h_ctr[2] = {0, 0};
@@ -794,10 +814,7 @@ ara_status ara_batch_rebuild(ara_batch b, const ara_layer *layers, int32_t n_lay
     if (n_layers != b->n) {
         // a batch whose size changes (a server's) launches directly from now
         // on instead of capturing a graph per size
-        if (b->exec) (void)hipGraphExecDestroy(b->exec);
-        if (b->graph) (void)hipGraphDestroy(b->graph);
-        b->exec = nullptr;
-        b->graph = nullptr;
+        drop_graph(b);
         b->tuned = false;
         b->use_graph = b->n == 0;
         b->n = n_layers;
@@ -822,7 +839,9 @@ ara_status ara_create_batch(ara_yet yet, const ara_layer *layers, int32_t n_laye
     (void)hipGetDevice(&b->device);
     const size_t C = (size_t)yet->catalog;
     const size_t rec_bytes = prec == ARA_FP64 ? 64 : 32;
-    hipError_t e = dev_alloc(&b->d_rec, C * rec_bytes);
+    hipError_t e = hipEventCreateWithFlags(&b->last_run, hipEventDisableTiming);
+    if (e != hipSuccess) b->last_run = nullptr;
+    if (e == hipSuccess) e = dev_alloc(&b->d_rec, C * rec_bytes);
     if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_count), C * sizeof(int32_t));
     if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_ctr), 2 * sizeof(unsigned long long));
     if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_ylts), sizeof(double *) * ARA_MAX_BATCH);
@@ -939,11 +958,48 @@ hipError_t capture_batch(ara_batch b) {
         e = hipStreamEndCapture(cs, &g);
         if (e == hipSuccess) e = le;
         if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-        if (e == hipSuccess) b->graph = g;
-        else if (g) (void)hipGraphDestroy(g);
+        if (e == hipSuccess) {
+            b->graph = g;
+            b->graph_tables = batch_tables(b);
+            b->graph_cfg = b->cfg;
+        } else {
+            b->exec = nullptr;
+            if (g) (void)hipGraphDestroy(g);
+        }
     }
     (void)hipStreamDestroy(cs);
     return e;
+}
+
+// The captured graph holds the table pointers, the layer count and the launch
+// shape as kernel arguments; a rebuild may have reallocated the overflow
+// arrays, so the graph is replayed only while they are unchanged.
+bool graph_current(const ara_batch b) {
+    const ara::BatchTables now = batch_tables(b);
+    const ara::BatchTables &was = b->graph_tables;
+    return b->exec && now.rec == was.rec && now.ovf_lid == was.ovf_lid && now.ovf_val == was.ovf_val &&
+           now.ylts == was.ylts && now.agg_ret == was.agg_ret && now.agg_lim == was.agg_lim &&
+           now.n_layers == was.n_layers && b->cfg.threads == b->graph_cfg.threads &&
+           b->cfg.wg_per_cu == b->graph_cfg.wg_per_cu;
+}
+
+// Launch the pass (graph replay or direct launch) and record the batch's
+// last-run event after it.
+ara_status launch_batch(ara_batch batch, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (!batch->use_graph) {
+        e = ara::launch_batch_pass(batch->yv, batch_tables(batch), batch->precision == ARA_FP64, batch->cfg, s);
+        if (e != hipSuccess) return hip_fail(e, "batch launch");
+    } else {
+        if (batch->exec && !graph_current(batch)) drop_graph(batch);
+        if (!batch->exec) {
+            e = capture_batch(batch);
+            if (e != hipSuccess) return hip_fail(e, "batch graph capture");
+        }
+        e = hipGraphLaunch(batch->exec, s);
+        if (e != hipSuccess) return hip_fail(e, "batch graph launch");
+    }
+    return ARA_OK;
 }
 
 }  // namespace
@@ -955,6 +1011,12 @@ ara_status ara_run_batch(ara_batch batch, double *const *d_ylts, void *hip_strea
     if (batch->yv.n_trials == 0) return ARA_OK;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     hipError_t e = hipSuccess;
+    // a run on another stream than the last one waits for the last run: it
+    // may overwrite the YLT pointers that run reads
+    if (batch->ran && s != batch->last_stream) {
+        e = hipStreamWaitEvent(s, batch->last_run, 0);
+        if (e != hipSuccess) return hip_fail(e, "ordering after the batch's last run");
+    }
     if (!std::equal(batch->h_ylts.begin(), batch->h_ylts.end(), d_ylts)) {
         for (int l = 0; l < batch->n; ++l) batch->h_ylts[l] = d_ylts[l];
         e = hipMemcpyAsync(batch->d_ylts, batch->h_ylts.data(), sizeof(double *) * batch->n, hipMemcpyHostToDevice,
@@ -967,23 +1029,18 @@ ara_status ara_run_batch(ara_batch batch, double *const *d_ylts, void *hip_strea
         for (int l = 0; l < batch->n && e == hipSuccess; ++l)
             e = ara::launch_fill_zero(d_ylts[l], batch->yv.n_trials, s);
         if (e != hipSuccess) return hip_fail(e, "zero YLTs");
-        return ARA_OK;
+    } else {
+        if (!batch->tuned) {
+            e = tune_batch(batch, s);
+            if (e != hipSuccess) return hip_fail(e, "batch launch tuning");
+        }
+        ara_status st = launch_batch(batch, s);
+        if (st != ARA_OK) return st;
     }
-    if (!batch->tuned) {
-        e = tune_batch(batch, s);
-        if (e != hipSuccess) return hip_fail(e, "batch launch tuning");
-    }
-    if (!batch->use_graph) {
-        e = ara::launch_batch_pass(batch->yv, batch_tables(batch), batch->precision == ARA_FP64, batch->cfg, s);
-        if (e != hipSuccess) return hip_fail(e, "batch launch");
-        return ARA_OK;
-    }
-    if (!batch->exec) {
-        e = capture_batch(batch);
-        if (e != hipSuccess) return hip_fail(e, "batch graph capture");
-    }
-    e = hipGraphLaunch(batch->exec, s);
-    if (e != hipSuccess) return hip_fail(e, "batch graph launch");
+    e = hipEventRecord(batch->last_run, s);
+    if (e != hipSuccess) return hip_fail(e, "recording the batch's run");
+    batch->ran = true;
+    batch->last_stream = s;
     return ARA_OK;
 }
 

@@ -127,3 +127,75 @@ def test_batch_over_empty_yet():
     lay = A.Layer(yet, spec, "fp64", "fused")
     outs = A.Batch(yet, [lay, lay]).run([torch.full((10,), 7.0, dtype=torch.float64, device="cuda") for _ in range(2)])
     assert all(np.array_equal(o.cpu().numpy(), np.zeros(10)) for o in outs)
+
+
+def _disjoint_layers(n, C, size, seed):
+    """n one-ELT layers over disjoint event ranges: no event is non-zero in
+    more than one layer, so the batch needs no overflow entries."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for l in range(n):
+        ids = np.arange(l * size, (l + 1) * size, dtype=np.int32) % C
+        out.append(W.LayerSpec([ids], [rng.uniform(1.0, 100.0, size)], np.zeros(1), np.full(1, np.inf),
+                               0.0, np.inf, 0.0, np.inf))
+    return out
+
+
+def _shared_layers(n, C, seed):
+    """n layers that all hold one ELT covering the whole catalogue (each with
+    its own terms): every event is non-zero in all n layers, so every record
+    spills n - 6 (FP64) or n - 5 (FP32C) entries into the overflow area."""
+    rng = np.random.default_rng(seed)
+    ids = np.arange(C, dtype=np.int32)
+    out = []
+    for l in range(n):
+        loss = rng.uniform(1.0, 1000.0, C)
+        out.append(W.LayerSpec([ids], [loss], np.array([float(l)]), np.array([900.0 - l]), float(l), 2000.0,
+                               float(10 * l), 1e7))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_batch_rebuild_same_size_larger_overflow(prec):
+    """Regression: a batch that replayed a captured graph and is then rebuilt
+    with the same number of layers but more overflow entries (its overflow
+    area is reallocated) must not replay the old graph's pointers; a run on a
+    second stream right after one on the first, and a rebuild right after a
+    run, are ordered after the earlier run by the library."""
+    T, C, n = 2500, 3000, 12
+    ids, off, _ = W.random_case(4242, T, 150.0, C, 1, 1)
+    yet = _yet(ids, off, T, C)
+    few = [A.Layer(yet, s, prec, "fused") for s in _disjoint_layers(n, C, 200, 1)]
+    many_specs = _shared_layers(n, C, 2)
+    many = [A.Layer(yet, s, prec, "fused") for s in many_specs]
+    single_few = [A.run_layer(yet, l).cpu().numpy() for l in few]
+    single_many = [A.run_layer(yet, l).cpu().numpy() for l in many]
+    b = A.Batch(yet, few)
+    small_bytes = b.device_bytes
+    outs = b.run()
+    outs = b.run(outs)  # the second run replays the captured graph
+    torch.cuda.synchronize()
+    for l in range(n):
+        assert np.array_equal(outs[l].cpu().numpy(), single_few[l]), ("few", l)
+    # no synchronisation between the run above and this rebuild
+    outs_a = b.run()
+    b.rebuild(many)
+    assert b.device_bytes > small_bytes  # the overflow area was reallocated
+    s2 = torch.cuda.Stream()
+    outs_b = b.run(stream=s2)
+    outs_c = b.run()  # default stream right after a run on s2
+    torch.cuda.synchronize()
+    for l in range(n):
+        assert np.array_equal(outs_a[l].cpu().numpy(), single_few[l]), ("before rebuild", l)
+        assert np.array_equal(outs_b[l].cpu().numpy(), single_many[l]), ("after rebuild", l)
+        assert np.array_equal(outs_c[l].cpu().numpy(), single_many[l]), ("after rebuild, other stream", l)
+    for l in (0, n - 1):
+        ref = oracle_run(ids, off, T, C, 0, many_specs[l])
+        assert_close_to_oracle(outs_b[l].cpu().numpy(), ref, prec)
+    # and back to the layers without overflow (no reallocation this time)
+    b.rebuild(few)
+    outs_d = b.run()
+    torch.cuda.synchronize()
+    for l in range(n):
+        assert np.array_equal(outs_d[l].cpu().numpy(), single_few[l]), ("rebuilt back", l)
+    b.close()
