@@ -271,6 +271,30 @@ ara_status ara_pml_tvar_many(const double *const *d_ylts, int32_t n_ylts, int64_
                              const double *h_return_periods, int32_t n_rp, double *h_pml, double *h_tvar,
                              void *hip_stream);
 
+/* PML and TVaR as ara_pml_tvar_many, for callers that cannot allocate
+ * memory or wait for the device (code being captured into a HIP graph, tight
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same results, bitwise, but every scratch buffer lives in a static device
+ * array of the library (about 1 MiB per GPU, held until the process ends)
+ * and the results stay on the device.
+ *   d_ylts, n_ylts, n_trials, h_return_periods, n_rp   as ara_pml_tvar_many,
+ *               with n_ylts * n_rp <= ARA_NOALLOC_MAX_SEL (else
+ *               ARA_ERR_UNSUPPORTED, nothing launched).
+ *   d_pml, d_tvar   caller-owned device binary64 [n_ylts][n_rp], row-major;
+ *               they must not overlap the YLTs.  A YLT holding NaN gets NaN
+ *               for its PML and TVaR (the call cannot return ARA_ERR_VALUE:
+ *               it does not wait for the device).
+ * ASYNCHRONOUS on hip_stream; no device or host allocation, no memset node,
+ * no synchronisation.  Every call on one GPU uses the same scratch: calls
+ * whose work overlaps on the device (e.g. queued on two streams without an
+ * order between them) race and give undefined results; calls ordered on one
+ * stream are safe (each starts by clearing what it needs at zero).  Errors:
+ * as ara_pml_tvar_many, detected on the host before any launch. */
+#define ARA_NOALLOC_MAX_SEL 64
+ara_status ara_pml_tvar_many_noalloc(const double *const *d_ylts, int32_t n_ylts, int64_t n_trials,
+                                     const double *h_return_periods, int32_t n_rp, double *d_pml, double *d_tvar,
+                                     void *hip_stream);
+
 /* Roll-up of year loss tables into programs, or of programs into a
  * portfolio.  Section III nests layers in programs and programs in a
  * portfolio and leaves their combination unstated; the reading here: group

@@ -26,6 +26,7 @@ ARA_FP64, ARA_FP32C = 0, 1
 ARA_LAYOUT_AUTO, ARA_LAYOUT_DIRECT, ARA_LAYOUT_SPARSE, ARA_LAYOUT_COMPACT, ARA_LAYOUT_FUSED = 0, 1, 2, 3, 4
 ARA_MAX_ELTS = 32
 ARA_MAX_BATCH = 64
+ARA_NOALLOC_MAX_SEL = 64
 
 _P = ctypes.c_void_p
 _I32, _I64, _D, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -50,6 +51,7 @@ SIGNATURES = {
     "ara_pool_free_slots": (_I32, [_P]),
     "ara_create_layer_from_pool": (_I32, [_P, _I32, _P, _P, _P, _D, _D, _D, _D, _P, _P]),
     "ara_pml_tvar_many": (_I32, [_P, _I32, _I64, _P, _I32, _P, _P, _P]),
+    "ara_pml_tvar_many_noalloc": (_I32, [_P, _I32, _I64, _P, _I32, _P, _P, _P]),
     "ara_rollup": (_I32, [_P, _I32, _P, _I32, _I64, _P, _P]),
     "ara_pml_tvar": (_I32, [_P, _I64, _P, _I32, _P, _P, _P]),
     "ara_layer_device_bytes": (_SZ, [_P]),

@@ -303,6 +303,24 @@ def pml_tvar_many(ylts: Sequence[torch.Tensor], return_periods: Sequence[float],
     return pml, tvar
 
 
+def pml_tvar_many_noalloc(ylts: Sequence[torch.Tensor], return_periods: Sequence[float], pml: torch.Tensor,
+                          tvar: torch.Tensor, stream=None):
+    """PML/TVaR into the device tensors pml, tvar (float64 [n_ylts, n_rp],
+    caller-allocated) with the library's static scratch: asynchronous, the
+    library allocates nothing."""
+    n = len(ylts)
+    T = ylts[0].numel()
+    for y in ylts:
+        _check_out(y, T, "ylt")
+    rp = _np(list(return_periods), np.float64)
+    _check_out(pml, n * len(rp), "pml")
+    _check_out(tvar, n * len(rp), "tvar")
+    ps = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ylts])
+    L.check(L.lib().ara_pml_tvar_many_noalloc(ps, n, int(T), _vp(rp), len(rp), ctypes.c_void_p(pml.data_ptr()),
+                                              ctypes.c_void_p(tvar.data_ptr()), ctypes.c_void_p(_stream(stream))))
+    return pml, tvar
+
+
 def rollup(ylts: Sequence[torch.Tensor], groups: Sequence[int], n_groups: int, out=None, stream=None):
     """Year loss tables of n_groups groups: group g is the trial-by-trial sum of
     ylts[l] for groups[l] == g, in increasing l (ara_rollup); asynchronous."""

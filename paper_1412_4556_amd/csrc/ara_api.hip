@@ -92,16 +92,20 @@ struct ara_batch_s {
 
 namespace {
 
-thread_local std::string g_err;
+// Message of the last failing call, per host thread, in a fixed buffer (so
+// that reporting an error allocates nothing).
+thread_local char g_err[512];
 
-ara_status fail(ara_status code, const std::string &msg) {
-    g_err = msg;
+ara_status fail(ara_status code, const char *msg) {
+    std::snprintf(g_err, sizeof(g_err), "%s", msg);
     return code;
 }
 
+ara_status fail(ara_status code, const std::string &msg) { return fail(code, msg.c_str()); }
+
 ara_status hip_fail(hipError_t e, const char *what) {
-    return fail(e == hipErrorOutOfMemory ? ARA_ERR_OOM : ARA_ERR_DEVICE,
-                std::string(what) + ": " + hipGetErrorString(e));
+    std::snprintf(g_err, sizeof(g_err), "%s: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? ARA_ERR_OOM : ARA_ERR_DEVICE;
 }
 
 bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
@@ -402,7 +406,7 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
 
 extern "C" {
 
-const char *ara_last_error(void) { return g_err.c_str(); }
+const char *ara_last_error(void) { return g_err; }
 
 int32_t ara_abi_version(void) { return 1; }
 
@@ -1145,6 +1149,24 @@ ara_status ara_pml_tvar_many(const double *const *d_ylts, int32_t n_ylts, int64_
         h_pml[i] = out[2 * i];
         h_tvar[i] = out[2 * i + 1];
     }
+    return ARA_OK;
+}
+
+ara_status ara_pml_tvar_many_noalloc(const double *const *d_ylts, int32_t n_ylts, int64_t n_trials,
+                                     const double *h_return_periods, int32_t n_rp, double *d_pml, double *d_tvar,
+                                     void *hip_stream) {
+    if (!d_ylts || !h_return_periods || !d_pml || !d_tvar) return fail(ARA_ERR_INVALID_ARG, "NULL pointer");
+    if (n_ylts < 1 || n_ylts > ARA_MAX_BATCH) return fail(ARA_ERR_INVALID_ARG, "n_ylts outside 1 .. ARA_MAX_BATCH");
+    for (int i = 0; i < n_ylts; ++i)
+        if (!d_ylts[i]) return fail(ARA_ERR_INVALID_ARG, "NULL YLT pointer");
+    int64_t k[16];
+    ara_status st = tail_sizes(n_trials, h_return_periods, n_rp, k);
+    if (st != ARA_OK) return st;
+    if (n_ylts * n_rp > ARA_NOALLOC_MAX_SEL)
+        return fail(ARA_ERR_UNSUPPORTED, "n_ylts * n_rp exceeds ARA_NOALLOC_MAX_SEL (the size of the static scratch)");
+    hipError_t e = ara::pml_tvar_noalloc(d_ylts, n_ylts, n_trials, k, n_rp, d_pml, d_tvar,
+                                         static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "PML/TVaR (no allocation)");
     return ARA_OK;
 }
 

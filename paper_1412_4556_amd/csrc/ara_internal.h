@@ -178,5 +178,9 @@ hipError_t launch_rollup(const RollupTables &a, int64_t n, hipStream_t s);
 // tail sizes k[r]; h_out[2 * (y * n_rp + r)] = PML, [... + 1] = TVaR.
 hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n, const int64_t *h_k, int32_t n_rp,
                            double *h_out, int32_t *h_nan, hipStream_t s);
+// The same selection over the library's static device scratch, results into
+// device arrays; asynchronous, allocates nothing.
+hipError_t pml_tvar_noalloc(const double *const *d_ylts, int32_t n_ylt, int64_t n, const int64_t *h_k, int32_t n_rp,
+                            double *d_pml, double *d_tvar, hipStream_t s);
 
 }  // namespace ara

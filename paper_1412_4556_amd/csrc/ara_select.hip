@@ -9,6 +9,7 @@
 // the ties at the selected value as (k - count) * value, all in binary64.
 // Many YLTs of the same length are handled by the same launches (one grid
 // row per YLT).
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -163,8 +164,8 @@ __device__ __forceinline__ void load_chunk(const double *__restrict__ y, long lo
 // are slow when many blocks hit the same bins).
 __global__ __launch_bounds__(kHistThreads) void k_sel_hist(YltPtrs ylts, long long n, SelState *__restrict__ st,
                                                            TailSizes tk, int n_rp, int n_sel, int pass,
-                                                           unsigned *__restrict__ hist, int *nan_flag,
-                                                           int *host_nan) {
+                                                           unsigned *__restrict__ hist, int *nan_flags,
+                                                           int *nan_seen, int *host_nan) {
     __shared__ unsigned h[kMaxRp * 256];
     __shared__ SelState s[kMaxRp];
     __shared__ int same_as[kMaxRp];  // first selection with the same prefix
@@ -178,9 +179,12 @@ __global__ __launch_bounds__(kHistThreads) void k_sel_hist(YltPtrs ylts, long lo
     for (int i = threadIdx.x; i < n_rp * 256; i += blockDim.x) h[i] = 0u;
     load_states(st, hist, tk, yi, n_rp, n_sel, pass, s);
     if (pass >= 2) clear_rows(hist, pass - 2, n_sel, yi, n_rp);
-    if (pass == 1 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-        store_host(host_nan, *nan_flag);
-        *nan_flag = 0;
+    if (pass == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
+        // every block of pass 0 has finished: move this YLT's flag on
+        const int f = nan_flags[yi];
+        nan_flags[yi] = 0;
+        nan_seen[yi] = f;
+        if (host_nan) store_host(host_nan + yi, f);
     }
     __syncthreads();
     if (threadIdx.x < (unsigned)n_rp) {
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(kHistThreads) void k_sel_hist(YltPtrs ylts, long lo
             for (int j = 0; j < kPer; ++j) v[j] = w[j];
         }
     }
-    if (saw_nan) atomicOr(nan_flag, 1);
+    if (saw_nan) atomicOr(&nan_flags[yi], 1);
     __syncthreads();
     unsigned *hp = hist + ((size_t)pass * n_sel + (size_t)yi * n_rp) * 256;
     for (int i = threadIdx.x; i < n_rp * 256; i += blockDim.x) {
@@ -294,9 +298,14 @@ __global__ __launch_bounds__(kThreads) void k_tail_sum(YltPtrs ylts, long long n
 
 // one block per selection; the partial sums of the kSumBlocks blocks are
 // added with a fixed tree, so the result does not depend on timing
+// Results go to pinned host memory (host_out, pairs per selection) or, when
+// dev_pml is set, to device arrays, where a YLT holding NaN gets NaN results.
 __global__ __launch_bounds__(kSumBlocks) void k_tail_finish(const SelState *st, const double *psum,
                                                             const unsigned long long *pcnt,
-                                                            unsigned *__restrict__ hist7, double *host_out) {
+                                                            unsigned *__restrict__ hist7, double *host_out,
+                                                            int n_rp, const int *__restrict__ nan_seen,
+                                                            double *__restrict__ dev_pml,
+                                                            double *__restrict__ dev_tvar) {
     __shared__ double ssum[kSumBlocks];
     __shared__ unsigned long long scnt[kSumBlocks];
     const int s = blockIdx.x;
@@ -315,10 +324,78 @@ __global__ __launch_bounds__(kSumBlocks) void k_tail_finish(const SelState *st, 
         const double pml = key_value(st[s].prefix);
         const long long k = st[s].k;
         const double ties = (double)(k - (long long)scnt[0]) * pml;
-        store_host(host_out + 2 * s, pml);
-        store_host(host_out + 2 * s + 1, (ssum[0] + ties) / (double)k);
+        const double tvar = (ssum[0] + ties) / (double)k;
+        if (dev_pml) {
+            const bool nan = nan_seen[s / n_rp] != 0;
+            dev_pml[s] = nan ? __longlong_as_double(0x7ff8000000000000LL) : pml;
+            dev_tvar[s] = nan ? __longlong_as_double(0x7ff8000000000000LL) : tvar;
+        } else {
+            store_host(host_out + 2 * s, pml);
+            store_host(host_out + 2 * s + 1, tvar);
+        }
     }
 }
+
+// Zeroes n words (the histograms and NaN flags a call of the no-allocation
+// form starts from).
+__global__ __launch_bounds__(kThreads) void k_zero_words(unsigned *__restrict__ p, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// Scratch layout for up to ms selections: NaN flags per YLT | flags moved on
+// by pass 1 | states per pass | histograms per pass | psum | pcnt.  Every
+// offset is a multiple of 16 bytes.
+struct SelLayout {
+    size_t seen, state, hist, psum, pcnt, total;
+};
+constexpr SelLayout layout_for(size_t ms) {
+    return SelLayout{sizeof(int) * kMaxYlt,
+                  2 * sizeof(int) * kMaxYlt,
+                  2 * sizeof(int) * kMaxYlt + sizeof(SelState) * (kPasses + 1) * ms,
+                  2 * sizeof(int) * kMaxYlt + sizeof(SelState) * (kPasses + 1) * ms + sizeof(unsigned) * 256 * kPasses * ms,
+                  2 * sizeof(int) * kMaxYlt + sizeof(SelState) * (kPasses + 1) * ms + sizeof(unsigned) * 256 * kPasses * ms +
+                      sizeof(double) * kSumBlocks * ms,
+                  2 * sizeof(int) * kMaxYlt + sizeof(SelState) * (kPasses + 1) * ms + sizeof(unsigned) * 256 * kPasses * ms +
+                      (sizeof(double) + sizeof(unsigned long long)) * kSumBlocks * ms};
+}
+static_assert(sizeof(SelState) == 32, "selection state size");
+
+// The launches of one call over a scratch of layout lay at base.
+hipError_t launch_select(char *base, const SelLayout &lay, const double *const *d_ylts, int32_t n_ylt, int64_t n,
+                         const int64_t *h_k, int32_t n_rp, int *host_nan, double *host_out, double *dev_pml,
+                         double *dev_tvar, hipStream_t s) {
+    int *nan_flags = reinterpret_cast<int *>(base);
+    int *nan_seen = reinterpret_cast<int *>(base + lay.seen);
+    SelState *st = reinterpret_cast<SelState *>(base + lay.state);
+    unsigned *hist = reinterpret_cast<unsigned *>(base + lay.hist);
+    double *psum = reinterpret_cast<double *>(base + lay.psum);
+    unsigned long long *pcnt = reinterpret_cast<unsigned long long *>(base + lay.pcnt);
+    const int n_sel = n_ylt * n_rp;
+    YltPtrs yp{};
+    for (int i = 0; i < n_ylt; ++i) yp.p[i] = d_ylts[i];
+    // tail sizes travel as a kernel argument (no host-to-device copy)
+    TailSizes tk{};
+    for (int r = 0; r < n_rp; ++r) tk.k[r] = (long long)h_k[r];
+    long long gx = (n + kHistChunk - 1) / kHistChunk;
+    const long long cap = n_ylt > 8 ? 32 : 256;
+    if (gx > cap) gx = cap;
+    for (int pass = 0; pass < kPasses; ++pass)
+        hipLaunchKernelGGL(k_sel_hist, dim3((unsigned)gx, n_ylt), dim3(kHistThreads), 0, s, yp, (long long)n, st, tk,
+                           n_rp, n_sel, pass, hist, nan_flags, nan_seen, host_nan);
+    hipLaunchKernelGGL(k_tail_sum, dim3(kSumBlocks, n_ylt), dim3(kThreads), 0, s, yp, (long long)n, st, tk, n_rp, n_sel,
+                       hist, psum, pcnt);
+    hipLaunchKernelGGL(k_tail_finish, dim3(n_sel), dim3(kSumBlocks), 0, s, st + (size_t)kPasses * n_sel, psum, pcnt,
+                       hist + (size_t)(kPasses - 1) * n_sel * 256, host_out, n_rp, nan_seen, dev_pml, dev_tvar);
+    return hipGetLastError();
+}
+
+// Scratch of the no-allocation form: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code uses only the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr int kNoAllocSel = ARA_NOALLOC_MAX_SEL;
+constexpr SelLayout kNoAllocLayout = layout_for(kNoAllocSel);
+static __device__ __align__(256) unsigned char scratch[kNoAllocLayout.total];
 
 // Library-owned scratch per device: device memory and a pinned host buffer
 // that the finishing kernels write the results into.  ara_pml_tvar is
@@ -351,21 +428,17 @@ hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     Scratch &sc = scratch_for(dev);
     std::lock_guard<std::mutex> g(sc.mu);
-    // device layout: nan flag (16 B) | states per pass | histograms per pass | psum | pcnt
-    // host layout:   nan flag (16 B) | PML/TVaR pairs
-    const size_t res_bytes = 16 + sizeof(double) * 2 * kMaxSel;
-    const size_t off_state = 16;
-    const size_t off_hist = off_state + sizeof(SelState) * (kPasses + 1) * kMaxSel;
-    const size_t off_psum = off_hist + sizeof(unsigned) * 256 * kPasses * kMaxSel;
-    const size_t off_pcnt = off_psum + sizeof(double) * kSumBlocks * kMaxSel;
-    const size_t total = off_pcnt + sizeof(unsigned long long) * kSumBlocks * kMaxSel;
+    // host layout: NaN flag per YLT | PML/TVaR pairs
+    constexpr SelLayout lay = layout_for(kMaxSel);
+    const size_t res_off = sizeof(int) * kMaxYlt;
+    const size_t res_bytes = res_off + sizeof(double) * 2 * kMaxSel;
     if (!sc.d) {
-        e = hipMalloc(&sc.d, total);
+        e = hipMalloc(&sc.d, lay.total);
         if (e != hipSuccess) {
             sc.d = nullptr;
             return e;
         }
-        e = hipMemset(sc.d, 0, off_psum);  // flag, states and histograms start at zero
+        e = hipMemset(sc.d, 0, lay.psum);  // flags, states and histograms start at zero
         if (e != hipSuccess) {
             (void)hipFree(sc.d);
             sc.d = nullptr;
@@ -386,46 +459,65 @@ hipError_t pml_tvar_device(const double *const *d_ylts, int32_t n_ylt, int64_t n
         }
     }
     char *base = static_cast<char *>(sc.d);
-    int *nan_flag = reinterpret_cast<int *>(base);
-    SelState *st = reinterpret_cast<SelState *>(base + off_state);
-    unsigned *hist = reinterpret_cast<unsigned *>(base + off_hist);
-    double *psum = reinterpret_cast<double *>(base + off_psum);
-    unsigned long long *pcnt = reinterpret_cast<unsigned long long *>(base + off_pcnt);
-    int *host_nan = static_cast<int *>(sc.hd);
-    double *host_out = reinterpret_cast<double *>(static_cast<char *>(sc.hd) + 16);
-    const int n_sel = n_ylt * n_rp;
-
     if (sc.dirty) {
         // the failed call's kernels may still run, on another stream
         if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
-        if ((e = hipMemsetAsync(nan_flag, 0, 16, s)) != hipSuccess) return e;
-        if ((e = hipMemsetAsync(hist, 0, off_psum - off_hist, s)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(base, 0, lay.seen, s)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(base + lay.hist, 0, lay.psum - lay.hist, s)) != hipSuccess) return e;
         sc.dirty = false;
     }
-    YltPtrs yp{};
-    for (int i = 0; i < n_ylt; ++i) yp.p[i] = d_ylts[i];
-    // tail sizes travel as a kernel argument (no host-to-device copy)
-    TailSizes tk{};
-    for (int r = 0; r < n_rp; ++r) tk.k[r] = (long long)h_k[r];
-    long long gx = (n + kHistChunk - 1) / kHistChunk;
-    const long long cap = n_ylt > 8 ? 32 : 256;
-    if (gx > cap) gx = cap;
+    int *host_nan = static_cast<int *>(sc.hd);
+    double *host_out = reinterpret_cast<double *>(static_cast<char *>(sc.hd) + res_off);
     sc.dirty = true;  // until the call has run to its end
-    for (int pass = 0; pass < kPasses; ++pass)
-        hipLaunchKernelGGL(k_sel_hist, dim3((unsigned)gx, n_ylt), dim3(kHistThreads), 0, s, yp, (long long)n, st, tk,
-                           n_rp, n_sel, pass, hist, nan_flag, host_nan);
-    hipLaunchKernelGGL(k_tail_sum, dim3(kSumBlocks, n_ylt), dim3(kThreads), 0, s, yp, (long long)n, st, tk, n_rp, n_sel,
-                       hist, psum, pcnt);
-    hipLaunchKernelGGL(k_tail_finish, dim3(n_sel), dim3(kSumBlocks), 0, s, st + (size_t)kPasses * n_sel, psum, pcnt,
-                       hist + (size_t)(kPasses - 1) * n_sel * 256, host_out);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = launch_select(base, lay, d_ylts, n_ylt, n, h_k, n_rp, host_nan, host_out, nullptr, nullptr, s);
+    if (e != hipSuccess) return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
     sc.dirty = false;
     const char *hb = static_cast<const char *>(sc.h);
-    *h_nan = *reinterpret_cast<const volatile int *>(hb);
-    const volatile double *ho = reinterpret_cast<const volatile double *>(hb + 16);
-    for (int i = 0; i < 2 * n_sel; ++i) h_out[i] = ho[i];
+    const volatile int *hn = reinterpret_cast<const volatile int *>(hb);
+    int any = 0;
+    for (int i = 0; i < n_ylt; ++i) any |= hn[i];
+    *h_nan = any;
+    const volatile double *ho = reinterpret_cast<const volatile double *>(hb + res_off);
+    for (int i = 0; i < 2 * n_ylt * n_rp; ++i) h_out[i] = ho[i];
     return hipSuccess;
+}
+
+hipError_t pml_tvar_noalloc(const double *const *d_ylts, int32_t n_ylt, int64_t n, const int64_t *h_k, int32_t n_rp,
+                            double *d_pml, double *d_tvar, hipStream_t s) {
+    if (n_ylt < 1 || n_ylt > kMaxYlt || n_rp < 1 || n_rp > kMaxRp || n_ylt * n_rp > kNoAllocSel)
+        return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    // the array's address on this device, looked up once per device with the
+    // device current
+    static std::atomic<char *> addr[kMaxDevices];
+    static std::mutex mu;
+    char *base = addr[dev].load(std::memory_order_acquire);
+    if (!base) {
+        std::lock_guard<std::mutex> g(mu);
+        base = addr[dev].load(std::memory_order_relaxed);
+        if (!base) {
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            if (!p) return hipErrorInvalidSymbol;
+            base = static_cast<char *>(p);
+            addr[dev].store(base, std::memory_order_release);
+        }
+    }
+    // the call's flags and histograms start at zero whatever an earlier call
+    // left behind (a kernel, not a memset node, so the call can be captured)
+    const SelLayout &lay = kNoAllocLayout;
+    const int n_sel = n_ylt * n_rp;
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(kThreads), 0, s, reinterpret_cast<unsigned *>(base),
+                       (long long)kMaxYlt);
+    hipLaunchKernelGGL(k_zero_words, dim3(64), dim3(kThreads), 0, s, reinterpret_cast<unsigned *>(base + lay.hist),
+                       (long long)kPasses * n_sel * 256);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_select(base, lay, d_ylts, n_ylt, n, h_k, n_rp, nullptr, nullptr, d_pml, d_tvar, s);
 }
 
 }  // namespace ara
