@@ -171,8 +171,9 @@ ara_status upload(ara::LayerHost &h, int slot, const T *src, size_t count, const
     return ARA_OK;
 }
 
-ara_status validate_elts(int32_t C, int32_t n_elts, const int32_t *h_elt_ids, const double *h_elt_losses,
-                         const int64_t *h_elt_sizes, std::vector<int64_t> &start) {
+// ELT sizes -> start offsets of the ELTs in the concatenated arrays.
+ara_status elt_starts(int32_t C, int32_t n_elts, const int32_t *h_elt_ids, const double *h_elt_losses,
+                      const int64_t *h_elt_sizes, std::vector<int64_t> &start) {
     start.assign(n_elts + 1, 0);
     for (int j = 0; j < n_elts; ++j) {
         if (h_elt_sizes[j] < 0) return fail(ARA_ERR_INVALID_ARG, "negative ELT size");
@@ -180,6 +181,14 @@ ara_status validate_elts(int32_t C, int32_t n_elts, const int32_t *h_elt_ids, co
         start[j + 1] = start[j] + h_elt_sizes[j];
     }
     if (start[n_elts] > 0 && (!h_elt_ids || !h_elt_losses)) return fail(ARA_ERR_INVALID_ARG, "NULL ELT arrays");
+    return ARA_OK;
+}
+
+// Every entry: ID in range, unique within its ELT, loss finite and >= 0.
+ara_status validate_elts(int32_t C, int32_t n_elts, const int32_t *h_elt_ids, const double *h_elt_losses,
+                         const int64_t *h_elt_sizes, std::vector<int64_t> &start) {
+    ara_status st = elt_starts(C, n_elts, h_elt_ids, h_elt_losses, h_elt_sizes, start);
+    if (st != ARA_OK) return st;
     // one bit per catalogue event (C / 8 bytes, cache-resident at the paper's
     // sizes), set by an ELT's IDs and cleared again before the next ELT
     std::vector<uint64_t> seen;
@@ -323,9 +332,51 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
         h.tab.n_fwords = (int32_t)n_fwords;
         h.tab.n_hwords = n_hwords;
         h.tab.hshift = hshift;
+        const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        if (ara::fused_build_fits(C, fshift, (int64_t)n)) {
+            // one launch builds the table from the ELTs as given (binary64
+            // losses) and checks every entry on the way
+            const size_t b_ids = up(n * sizeof(int32_t)), b_loss = up(n * sizeof(double));
+            const size_t need = b_ids + b_loss + 256;
+            Staging &sg = staging_for(dev);
+            std::lock_guard<std::mutex> g(sg.mu);
+            if (sg.cap < need) {
+                if (sg.d) (void)hipFree(sg.d);
+                sg.d = nullptr;
+                sg.cap = 0;
+                e = dev_alloc(&sg.d, need);
+                if (e != hipSuccess) {
+                    sg.d = nullptr;
+                    return hip_fail(e, "device allocation of the build staging");
+                }
+                sg.cap = need;
+            }
+            char *base = static_cast<char *>(sg.d);
+            int32_t *d_ids = reinterpret_cast<int32_t *>(base);
+            double *d_loss = reinterpret_cast<double *>(base + b_ids);
+            int *d_flags = reinterpret_cast<int *>(base + b_ids + b_loss);
+            hipStream_t s = ara::internal_stream();
+            if (!s) return fail(ARA_ERR_DEVICE, "no set-up stream");
+            e = hipMemsetAsync(d_flags, 0, sizeof(int), s);
+            if (e == hipSuccess && n) e = hipMemcpyAsync(d_ids, ids, n * sizeof(int32_t), hipMemcpyHostToDevice, s);
+            if (e == hipSuccess && n) e = hipMemcpyAsync(d_loss, loss, n * sizeof(double), hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return hip_fail(e, "copy of the layer's ELTs");
+            std::vector<int32_t> order(J);
+            for (int j = 0; j < J; ++j) order[j] = j;
+            e = ara::launch_fused_build(h, d_ids, d_loss, true, start.data(), order.data(), J, d_flags, s);
+            int flags = 0;
+            if (e == hipSuccess) e = hipMemcpyAsync(&flags, d_flags, sizeof(int), hipMemcpyDeviceToHost, s);
+            // the staging is reused by the next build only after this wait
+            const hipError_t se = hipStreamSynchronize(s);
+            if (e == hipSuccess) e = se;
+            if (e != hipSuccess) return hip_fail(e, "building the fused table");
+            if (flags & 1) return fail(ARA_ERR_EVENT_RANGE, "ELT event ID outside [0, catalog_size)");
+            if (flags & 2) return fail(ARA_ERR_DUP_EVENT, "duplicate event ID in one ELT");
+            if (flags & 4) return fail(ARA_ERR_VALUE, "ELT loss must be finite and >= 0");
+            return ARA_OK;
+        }
         // staging: IDs, losses in the layer's arithmetic and, for FP32C, the
         // compensation terms of the binary32 sums (256-byte aligned parts)
-        const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
         const size_t b_ids = up(n * sizeof(int32_t)), b_loss = up(n * sizeof(T));
         const size_t b_lo = sizeof(T) == sizeof(float) ? up((size_t)C * sizeof(float)) : 0;
         const size_t need = b_ids + b_loss + b_lo > 256 ? b_ids + b_loss + b_lo : 256;
@@ -481,8 +532,18 @@ ara_status ara_create_layer(ara_yet yet, int32_t n_elts, const int32_t *h_elt_id
     if (!h_elt_sizes || !h_ret || !h_lim) return fail(ARA_ERR_INVALID_ARG, "NULL term or size array");
     const int32_t C = yet->catalog;
     std::vector<int64_t> start;
-    ara_status vst = validate_elts(C, n_elts, h_elt_ids, h_elt_losses, h_elt_sizes, start);
+    ara_status vst = elt_starts(C, n_elts, h_elt_ids, h_elt_losses, h_elt_sizes, start);
     if (vst != ARA_OK) return vst;
+    // a fused layer built in one launch has its entries checked by that
+    // launch; every other layer checks them here
+    int32_t fshift = 0, n_fwords = 0, n_hwords = 0, hshift = 0;
+    filter_geometry(C, fshift, n_fwords, n_hwords, hshift);
+    const bool fused = layout == ARA_LAYOUT_AUTO || layout == ARA_LAYOUT_FUSED;
+    const bool gpu_checked = fused && ara::fused_build_fits(C, fshift, start[n_elts]);
+    if (!gpu_checked) {
+        vst = validate_elts(C, n_elts, h_elt_ids, h_elt_losses, h_elt_sizes, start);
+        if (vst != ARA_OK) return vst;
+    }
     vst = validate_terms(n_elts, h_ret, h_lim, occ_ret, occ_lim, agg_ret, agg_lim);
     if (vst != ARA_OK) return vst;
 
@@ -720,8 +781,11 @@ ara_status ara_create_layer_from_pool(ara_pool pool, int32_t n_elts, const int32
     h.bytes = pool->slot_bytes;
     set_terms(h, n_elts, h_ret, h_lim, occ_ret, occ_lim, agg_ret, agg_lim);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    hipError_t e = ara::launch_pool_layer(h, static_cast<const int32_t *>(pool->d_ids), pool->d_loss, pool->off.data(),
-                                          h_elt_index, n_elts, static_cast<float *>(pool->lo[slot]), s);
+    hipError_t e = ara::launch_fused_build(h, static_cast<const int32_t *>(pool->d_ids), pool->d_loss, false,
+                                           pool->off.data(), h_elt_index, n_elts, nullptr, s);
+    if (e == hipErrorNotSupported)
+        e = ara::launch_pool_layer(h, static_cast<const int32_t *>(pool->d_ids), pool->d_loss, pool->off.data(),
+                                   h_elt_index, n_elts, static_cast<float *>(pool->lo[slot]), s);
     if (e == hipSuccess) e = hipEventRecord(L->ready, s);
     if (e != hipSuccess) {
         std::lock_guard<std::mutex> g(pool->mu);

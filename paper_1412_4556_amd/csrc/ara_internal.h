@@ -161,6 +161,27 @@ size_t batch_lds_bytes(int32_t n_layers, int threads);
 // binary32 scratch [catalog] for FP32C, else unused.
 hipError_t launch_pool_layer(LayerHost &L, const int32_t *d_ids, const void *d_loss, const int64_t *h_off,
                              const int32_t *h_idx, int32_t n, float *d_lo, hipStream_t s);
+// The same table in one launch (plus one clearing the hashed filter) when
+// fused_build_fits: one work-group per kBuildRange catalogue events.
+// host_losses: d_loss holds the ELTs' binary64 losses as given by the host,
+// and the kernel validates every entry into *d_flags (bit 1 ID out of range,
+// 2 duplicate ID in one ELT, 4 bad loss; cleared by the caller); else
+// d_loss holds the pool's values (the layer's precision) and d_flags is
+// unused.  Returns hipErrorNotSupported when the layer does not fit.
+constexpr int kBuildRange = 8192;
+constexpr int kBuildThreads = 1024;
+constexpr int kBuildUnroll = 16;
+constexpr int64_t kBuildReadBudget = (int64_t)1 << 30;  // IDs read over all work-groups
+struct BuildSegs {
+    int64_t begin[kMaxElts];  // ELT j of the layer: entries begin[j] .. begin[j] + count[j]
+    int64_t count[kMaxElts];
+    double ret[kMaxElts];     // FT1 terms (binary64; converted like the layer's terms)
+    double lim[kMaxElts];
+    int32_t n;
+};
+bool fused_build_fits(int64_t catalog, int32_t fshift, int64_t n_entries);
+hipError_t launch_fused_build(LayerHost &L, const int32_t *d_ids, const void *d_loss, bool host_losses,
+                              const int64_t *h_off, const int32_t *h_idx, int32_t n, int *d_flags, hipStream_t s);
 // d[0 .. n) = 0 with a kernel (no memset node if the caller captures a graph)
 hipError_t launch_fill_zero(double *d, int64_t n, hipStream_t s);
 

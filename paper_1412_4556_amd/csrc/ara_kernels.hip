@@ -12,6 +12,7 @@
 // the wave (DPP row shifts and row broadcasts) with a carry between chunks,
 // which yields the cumulative loss S_k after every event.
 #include "ara_internal.h"
+#include "ara_index.h"
 
 #include <atomic>
 #include <map>
@@ -336,7 +337,7 @@ __device__ __forceinline__ void load4(const YetView &y, int64_t p, const TrialRa
     }
 }
 
-__device__ __forceinline__ int64_t chunk_start(const YetView &y, int64_t b) { return y.aligned16 ? (b & ~3LL) : b; }
+__device__ __forceinline__ int64_t chunk_start(const YetView &y, int64_t b) { return ara::chunk_start(y.aligned16 != 0, b); }
 
 // --------------------------------------------------------------------------------------------
 // kernels
@@ -457,27 +458,19 @@ __device__ __forceinline__ uint32_t load_group(const YetView &y, const TrialRang
     uint32_t valid = 0;  // bit 4c+v: element v of chunk c lies in the trial
     // (FIXED: a trial ends on a granule boundary; the YET-wide clamp costs
     // at most one granule per lane and no extra registers)
-    const int64_t lim = (FIXED || r.e <= r.b) ? last_granule : ((r.e - 1) & ~3LL);
+    const int64_t lim = load_limit(FIXED, r.b, r.e, last_granule);
 #pragma unroll
     for (int c = 0; c < G; ++c) {
-        const int64_t p = base + c * 4 * kWave + 4 * lane;
+        const int64_t p = base + c * kChunkEvents + 4 * lane;
         if (ALIGNED) {
-            const int64_t q = p < lim ? p : lim;
-            const int4 v = stream_ids4(y.ids + q);
+            const int4 v = stream_ids4(y.ids + clamped_granule(p, lim));
             g.id[c][0] = v.x; g.id[c][1] = v.y; g.id[c][2] = v.z; g.id[c][3] = v.w;
-            if (FIXED) {
-                valid |= (p < r.e ? 0xfu : 0u) << (4 * c);
-            } else {
-                const int64_t lo64 = r.b - p, hi64 = r.e - p;
-                const int lo = lo64 < 0 ? 0 : (int)(lo64 > 4 ? 4 : lo64);
-                const int hi = hi64 < 0 ? 0 : (int)(hi64 > 4 ? 4 : hi64);
+            const uint32_t m = granule_valid(FIXED, p, r.b, r.e);
+            if (!FIXED) {
 #pragma unroll
-                for (int v4 = 0; v4 < 4; ++v4) {
-                    const bool in = (v4 >= lo) & (v4 < hi);
-                    g.id[c][v4] = in ? g.id[c][v4] : 0;
-                    valid |= (in ? 1u : 0u) << (4 * c + v4);
-                }
+                for (int v4 = 0; v4 < 4; ++v4) g.id[c][v4] = ((m >> v4) & 1u) ? g.id[c][v4] : 0;
             }
+            valid |= m << (4 * c);
         } else {
             load4(y, p, r, g.id[c]);
 #pragma unroll
@@ -1043,6 +1036,120 @@ __global__ void k_hash_filter(const T *__restrict__ occ, int64_t catalog, int32_
         }
 }
 
+// A layer's fused table in one launch.  Work-group g owns the catalogue
+// events [g R, (g + 1) R) (R = kBuildRange) and keeps their sums in LDS: it
+// reads the IDs of every ELT of the layer, in layer order, and adds FT1 of
+// the losses of its own events (an ELT holds an event at most once, so no
+// two threads of one ELT add to the same slot; a barrier separates the
+// ELTs), which is the order of k_pool_add.  It then applies the occurrence
+// terms, writes its range of the table and its words of the block filter
+// (a range covers whole filter words) and sets the hashed filter's bits of
+// its non-zero events (words cleared beforehand).  Bitwise the table of
+// k_pool_zero / k_pool_add / k_pool_finish and the filter kernels.
+// CHECK (ELTs from the host): also validates every entry and reports in
+// *flags: 1 an ID outside [0, catalog), 2 an ID twice in one ELT, 4 a loss
+// that is negative, infinite or NaN (the table is then not used).
+// LT: type of the stored losses (binary64 from the host; the pool's own
+// type for pool layers); the conversion to T is the one the host would do.
+template <typename T, typename LT, bool CHECK>
+__global__ __launch_bounds__(kBuildThreads) void k_fused_build(const int32_t *__restrict__ ids,
+                                                               const LT *__restrict__ loss, BuildSegs sg,
+                                                               int32_t catalog, T occ_ret, T occ_lim,
+                                                               T *__restrict__ occ, uint32_t *__restrict__ filt,
+                                                               int32_t n_fwords, int32_t fshift,
+                                                               uint32_t *__restrict__ hwords, int32_t n_hwords,
+                                                               int32_t hshift, int *flags) {
+    extern __shared__ uint64_t build_lds[];
+    T *hi = reinterpret_cast<T *>(build_lds);
+    float *lo = reinterpret_cast<float *>(hi + kBuildRange);  // FP32C: compensation terms
+    int *stamp = reinterpret_cast<int *>(lo + (sizeof(T) == sizeof(float) ? kBuildRange : 0));  // CHECK
+    const int64_t base = (int64_t)blockIdx.x * kBuildRange;
+    const int64_t top = base + kBuildRange < (int64_t)catalog + 1 ? base + kBuildRange : (int64_t)catalog + 1;
+    const uint32_t nloc = (uint32_t)(top - base);
+    for (int k = threadIdx.x; k < kBuildRange; k += blockDim.x) {
+        hi[k] = T(0);
+        if (sizeof(T) == sizeof(float)) lo[k] = 0.0f;
+        if (CHECK) stamp[k] = -1;
+    }
+    __syncthreads();
+    int bad = 0;
+    for (int j = 0; j < sg.n; ++j) {
+        const int64_t b = sg.begin[j], m = sg.count[j];
+        const T r = (T)sg.ret[j], u = (T)sg.lim[j];
+        for (int64_t i0 = 0; i0 < m; i0 += (int64_t)kBuildUnroll * blockDim.x) {
+            int32_t e[kBuildUnroll];
+#pragma unroll
+            for (int q = 0; q < kBuildUnroll; ++q) {
+                const int64_t i = i0 + (int64_t)q * blockDim.x + threadIdx.x;
+                e[q] = i < m ? ids[b + i] : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < kBuildUnroll; ++q) {
+                const int64_t i = i0 + (int64_t)q * blockDim.x + threadIdx.x;
+                if (i >= m) continue;
+                if (CHECK && (e[q] < 0 || e[q] >= catalog)) {
+                    bad |= 1;
+                    continue;
+                }
+                const uint32_t off = (uint32_t)((int64_t)e[q] - base);
+                if (off >= nloc) continue;
+                const LT l = loss[b + i];
+                if (CHECK) {
+                    if (!(l >= LT(0) && l <= __DBL_MAX__)) bad |= 4;
+                    if (atomicExch(&stamp[off], j) == j) bad |= 2;
+                }
+                const T x = clamp_excess((T)l, r, u);
+                if (sizeof(T) == sizeof(double)) {
+                    hi[off] += x;
+                } else {
+                    float sum, err;
+                    two_sum((float)hi[off], (float)x, sum, err);
+                    hi[off] = (T)sum;
+                    lo[off] += err;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (CHECK && bad) atomicOr(flags, bad);
+    // occurrence terms; the zero slot occ[catalog] stays 0
+    for (uint32_t k = threadIdx.x; k < nloc; k += blockDim.x) {
+        const int64_t e = base + k;
+        const T v = sizeof(T) == sizeof(double) ? hi[k] : (T)((float)hi[k] + lo[k]);
+        const T o = e < catalog ? clamp_excess(v, occ_ret, occ_lim) : T(0);
+        occ[e] = o;
+        hi[k] = o;
+    }
+    __syncthreads();
+    // block filter words of the range: bit b of word w is set iff an event of
+    // block 32 w + b (2^fshift events) has a non-zero occurrence loss
+    const int wshift = 5 + fshift;
+    const int64_t w0 = base >> wshift;
+    const int n_w = kBuildRange >> wshift;
+    for (int q = threadIdx.x; q < n_w; q += blockDim.x) {
+        const int64_t w = w0 + q;
+        if (w >= n_fwords) continue;
+        uint32_t bits = 0;
+        const int per = 1 << fshift;
+        for (int bb = 0; bb < 32; ++bb) {
+            const int k0 = (q << wshift) + (bb << fshift);
+            uint32_t any = 0;
+            for (int t = 0; t < per; ++t) any |= hi[k0 + t] != T(0) ? 1u : 0u;
+            bits |= any << bb;
+        }
+        filt[w] = bits;
+    }
+    if (n_hwords > 0) {
+        for (uint32_t k = threadIdx.x; k < nloc; k += blockDim.x) {
+            const int64_t e = base + k;
+            if (e < catalog && hi[k] != T(0)) {
+                const uint32_t h = hash_slot((uint32_t)e, hshift);
+                atomicOr(&hwords[h >> 5], 1u << (h & 31u));
+            }
+        }
+    }
+}
+
 // One read of every ID: the IDs before the first 16-byte boundary and after
 // the last whole 16-byte granule one by one, the granules with non-temporal
 // 16-byte loads: a wave reads 8 KiB in a row (eight loads in flight per
@@ -1297,6 +1404,69 @@ hipError_t launch_pool_layer(LayerHost &L, const int32_t *d_ids, const void *d_l
                              const int32_t *h_idx, int32_t n, float *d_lo, hipStream_t s) {
     if (L.precision == ARA_FP32C) return pool_layer_t<float>(L, L.t32, d_ids, d_loss, h_off, h_idx, n, d_lo, s);
     return pool_layer_t<double>(L, L.t64, d_ids, d_loss, h_off, h_idx, n, nullptr, s);
+}
+
+namespace {
+template <typename T>
+const Terms<T> &terms_of(const LayerHost &L);
+template <>
+const Terms<double> &terms_of<double>(const LayerHost &L) {
+    return L.t64;
+}
+template <>
+const Terms<float> &terms_of<float>(const LayerHost &L) {
+    return L.t32;
+}
+}  // namespace
+
+bool fused_build_fits(int64_t catalog, int32_t fshift, int64_t n_entries) {
+    if ((kBuildRange >> (5 + fshift)) < 1 || ((kBuildRange >> (5 + fshift)) << (5 + fshift)) != kBuildRange) return false;
+    const int64_t groups = (catalog + 1 + kBuildRange - 1) / kBuildRange;
+    // every work-group reads every ID of the layer
+    return groups * (n_entries > 0 ? n_entries : 1) <= kBuildReadBudget;
+}
+
+namespace {
+template <typename T, typename LT, bool CHECK>
+hipError_t fused_build_t(LayerHost &L, const int32_t *d_ids, const void *d_loss, const int64_t *h_off,
+                         const int32_t *h_idx, int32_t n, int *d_flags, hipStream_t s) {
+    BuildSegs sg{};
+    int64_t total = 0;
+    for (int j = 0; j < n; ++j) {
+        sg.begin[j] = h_off[h_idx[j]];
+        sg.count[j] = h_off[h_idx[j] + 1] - h_off[h_idx[j]];
+        sg.ret[j] = L.t64.ret[j];
+        sg.lim[j] = L.t64.lim[j];
+        total += sg.count[j];
+    }
+    sg.n = n;
+    if (!fused_build_fits(L.catalog, L.tab.fshift, total)) return hipErrorNotSupported;
+    const Terms<T> &t = terms_of<T>(L);
+    auto kern = &k_fused_build<T, LT, CHECK>;
+    const int lds = (int)(kBuildRange * (sizeof(T) + (sizeof(T) == sizeof(float) ? 4 : 0) + (CHECK ? 4 : 0)));
+    hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(kern), lds);
+    if (e != hipSuccess) return e;
+    uint32_t *hw = const_cast<uint32_t *>(L.tab.filt) + L.tab.n_fwords;
+    if (L.tab.n_hwords > 0)
+        hipLaunchKernelGGL((k_fill_zero<uint32_t>), dim3(64), dim3(256), 0, s, hw, (int64_t)L.tab.n_hwords);
+    const int64_t groups = ((int64_t)L.catalog + 1 + kBuildRange - 1) / kBuildRange;
+    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kBuildThreads), lds, s, d_ids, static_cast<const LT *>(d_loss),
+                       sg, L.catalog, t.occ_ret, t.occ_lim, static_cast<T *>(const_cast<void *>(L.tab.occ)),
+                       const_cast<uint32_t *>(L.tab.filt), L.tab.n_fwords, L.tab.fshift, hw, L.tab.n_hwords,
+                       L.tab.hshift, d_flags);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_fused_build(LayerHost &L, const int32_t *d_ids, const void *d_loss, bool host_losses,
+                              const int64_t *h_off, const int32_t *h_idx, int32_t n, int *d_flags, hipStream_t s) {
+    if (host_losses) {
+        // binary64 losses straight from the host, validated on the way
+        if (L.precision == ARA_FP32C) return fused_build_t<float, double, true>(L, d_ids, d_loss, h_off, h_idx, n, d_flags, s);
+        return fused_build_t<double, double, true>(L, d_ids, d_loss, h_off, h_idx, n, d_flags, s);
+    }
+    if (L.precision == ARA_FP32C) return fused_build_t<float, float, false>(L, d_ids, d_loss, h_off, h_idx, n, nullptr, s);
+    return fused_build_t<double, double, false>(L, d_ids, d_loss, h_off, h_idx, n, nullptr, s);
 }
 
 hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t s) {

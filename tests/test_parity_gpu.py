@@ -437,3 +437,59 @@ def test_create_errors():
     assert L.ERRORS.get(rc) == "ARA_ERR_INVALID_ARG"
     y2, mx = A.run_layer_max_occurrence(yet, lay)
     assert y2.cpu().tolist() == [3.0, 4.0] and mx.cpu().tolist() == [3.0, 4.0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_fused_build_at_paper_catalogue(prec):
+    """The one-launch fused build at the paper's catalogue (2M events, 16 ELTs
+    of 20,000): its table gives bitwise the YLT of the compact layout, and it
+    finds a duplicate ID, an out-of-range ID and a bad loss anywhere in the
+    ELTs (the checks run on the GPU for this layout)."""
+    C = 2_000_000
+    ids, off, spec = W.random_case(1999, 3000, 400.0, C, 16, 20_000)
+    T = len(off) - 1
+    yet = A.yet_from_numpy(ids, off, T, C)
+    fused = A.Layer(yet, spec, prec, "fused")
+    compact = A.Layer(yet, spec, prec, "compact")
+    yf = A.run_layer(yet, fused).cpu().numpy()
+    yc = A.run_layer(yet, compact).cpu().numpy()
+    assert np.array_equal(yf, yc)
+    # the same table from a pool of the same ELTs
+    P = A.Pool(yet, spec.elt_ids, spec.elt_losses, prec, max_layers=2)
+    lp = P.layer(np.arange(16, dtype=np.int32), spec.ret, spec.lim, spec.occ_ret, spec.occ_lim, spec.agg_ret,
+                 spec.agg_lim)
+    assert np.array_equal(A.run_layer(yet, lp).cpu().numpy(), yf)
+    lp.close()
+    ref = oracle_run(ids, off, T, C, 0, spec)
+    assert_close_to_oracle(yf, ref, prec)
+
+    def broken(j, pos, value=None, loss=None):
+        e_ids = [a.copy() for a in spec.elt_ids]
+        e_loss = [a.copy() for a in spec.elt_losses]
+        if value is not None:
+            e_ids[j][pos] = value
+        if loss is not None:
+            e_loss[j][pos] = loss
+        return W.LayerSpec(e_ids, e_loss, spec.ret, spec.lim, spec.occ_ret, spec.occ_lim, spec.agg_ret, spec.agg_lim)
+
+    cases = [(9, 19_990, int(spec.elt_ids[9][5]), None, "ARA_ERR_DUP_EVENT"),
+             (0, 0, int(spec.elt_ids[0][19_999]), None, "ARA_ERR_DUP_EVENT"),
+             (15, 19_999, C, None, "ARA_ERR_EVENT_RANGE"),
+             (3, 7, -5, None, "ARA_ERR_EVENT_RANGE"),
+             (0, 11_111, None, float("inf"), "ARA_ERR_VALUE"),
+             (12, 3, None, float("nan"), "ARA_ERR_VALUE"),
+             (7, 19_000, None, -1e-300, "ARA_ERR_VALUE")]
+    for j, pos, value, loss, want in cases:
+        with pytest.raises(L.AraError) as ei:
+            A.Layer(yet, broken(j, pos, value, loss), prec, "fused")
+        assert ei.value.name == want, (j, pos, value, loss)
+    # an ID in several ELTs of the layer is allowed
+    e_ids = [a.copy() for a in spec.elt_ids]
+    in4 = set(spec.elt_ids[4].tolist())
+    e_ids[4][0] = next(x for x in spec.elt_ids[3].tolist() if x not in in4)
+    ok = W.LayerSpec(e_ids, spec.elt_losses, spec.ret, spec.lim, spec.occ_ret, spec.occ_lim, spec.agg_ret,
+                     spec.agg_lim)
+    A.Layer(yet, ok, prec, "fused").close()
+    # and a valid build still works after the failed ones
+    again = A.Layer(yet, spec, prec, "fused")
+    assert np.array_equal(A.run_layer(yet, again).cpu().numpy(), yf)
