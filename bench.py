@@ -7,9 +7,12 @@ ELTs x 20,000 events (lognormal(10, 2) losses, per-ELT retention/limit at the
 10th/90th percentile, occurrence 1e5/1e7, aggregate 1e6/5e7), synthetic and
 seeded, resident in HBM before timing starts.
 
-One step = the trial pass of the layer over every trial (YLT written to HBM)
-plus PML/TVaR at 1-in-100 and 1-in-250 returned to the host.  Prints one JSON
-line on stdout; progress goes to stderr.
+One step = the layer's fused table built on the GPU from its 16 ELTs, which
+are resident in HBM (steps 1-3 of the method for every catalogue event: the
+per-ELT terms, the sum over the ELTs, the occurrence terms), the trial pass
+over every trial (the cumulative sum and the aggregate terms, YLT written to
+HBM), and PML/TVaR at 1-in-100 and 1-in-250 returned to the host.  Prints one
+JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
@@ -58,12 +61,30 @@ def cpu_model():
     return "unknown"
 
 
-def host_threads():
+def host_cpus():
+    """What the host offers this process: logical CPUs, the CPUs it may run
+    on, and the thread count the machine sets for OpenMP (on a GPU machine of
+    this pool: the CPU share of one GPU)."""
     try:
-        n = len(os.sched_getaffinity(0))
+        aff = len(os.sched_getaffinity(0))
     except Exception:
-        n = os.cpu_count() or 1
-    return max(1, min(n, 16))
+        aff = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS")
+    return {"logical_cpus": os.cpu_count(), "affinity_cpus": aff, "omp_num_threads": omp,
+            "cpu_model": cpu_model()}
+
+
+def host_threads():
+    """Threads of the CPU baseline: every CPU this process may run on, capped
+    by OMP_NUM_THREADS when the machine sets it (the machine's CPU share)."""
+    info = host_cpus()
+    n = info["affinity_cpus"]
+    if info["omp_num_threads"]:
+        try:
+            n = min(n, int(info["omp_num_threads"]))
+        except ValueError:
+            pass
+    return max(1, n)
 
 
 def time_layer(A, torch, yet, lay, ylt, steps, warmup, rps, with_pml=True):
@@ -89,7 +110,98 @@ def time_layer(A, torch, yet, lay, ylt, steps, warmup, rps, with_pml=True):
     return (t1 - t0) * 1e3 / steps, sum(k_ms) / len(k_ms), min(k_ms), res
 
 
-def cpu_baseline(wl, spec, target_s, gpu_ylt=None, gpu_pml_tvar=None, rps=()):
+def time_step(A, torch, yet, pool, spec, ylt, steps, warmup, rps):
+    """The headline step (fused table from the device-resident ELTs, trial
+    pass, PML/TVaR to the host).  Returns the wall time per step, the mean
+    build and pass times (HIP events on the launch stream), the fastest pass
+    and the last step's PML/TVaR."""
+    import numpy as np
+
+    stream = torch.cuda.current_stream()
+    idx = np.arange(spec.n_elts, dtype=np.int32)
+
+    def one(ev=None):
+        if ev:
+            ev[0].record(stream)
+        lay = pool.layer(idx, spec.ret, spec.lim, spec.occ_ret, spec.occ_lim, spec.agg_ret, spec.agg_lim,
+                         stream=stream)
+        if ev:
+            ev[1].record(stream)
+        A.run_layer(yet, lay, out=ylt, stream=stream)
+        if ev:
+            ev[2].record(stream)
+        res = A.pml_tvar(ylt, rps, stream=stream)
+        lay.close()  # the slot's next build is queued behind this pass on the same stream
+        return res
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    res = None
+    for i in range(steps):
+        res = one(evs[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    b_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    p_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    return (t1 - t0) * 1e3 / steps, sum(b_ms) / steps, sum(p_ms) / steps, min(p_ms), res
+
+
+def error_report(y, ref, tol, gpu_pml_tvar=None, rps=()):
+    """Error of a GPU year loss table against the oracle's, per trial:
+    relative to the oracle's year loss (over trials where it is > 0), to the
+    trial's gross looked-up loss G and to its cumulative occurrence loss S;
+    and, with the GPU's PML/TVaR, their relative error against the oracle's
+    values from its own table."""
+    import numpy as np
+
+    from oracle import oracle
+
+    err = np.abs(np.asarray(y) - ref["ylt"])
+    pos = ref["ylt"] > 0
+    rel = err[pos] / ref["ylt"][pos]
+    spos = ref["occ_sum"] > 0
+    out = {"trials": int(len(err)),
+           "max_rel_err": float(rel.max()) if pos.any() else 0.0,
+           "mean_rel_err": float(rel.mean()) if pos.any() else 0.0,
+           "max_err_over_gross": float((err / np.maximum(ref["gross"], 1e-300)).max()) if len(err) else 0.0,
+           "max_err_over_S": float((err[spos] / ref["occ_sum"][spos]).max()) if spos.any() else 0.0,
+           "trials_over_tol_gross": int((err > tol * ref["gross"]).sum()),
+           "bitwise_equal_trials": int((np.asarray(y) == ref["ylt"]).sum())}
+    if gpu_pml_tvar is not None:
+        op, ot = oracle.pml_tvar(ref["ylt"], rps)
+        gp, gt = gpu_pml_tvar
+        nz = lambda a: np.where(a == 0, 1.0, np.abs(a))
+        out["pml_rel_err"] = [float(v) for v in np.abs(np.asarray(gp) - op) / nz(op)]
+        out["tvar_rel_err"] = [float(v) for v in np.abs(np.asarray(gt) - ot) / nz(ot)]
+    return out
+
+
+def precision_runs(A, W, torch):
+    """The precision workload (10k Poisson(1000) trials, 4 ELTs of Pareto
+    losses, two term sets) through the GPU in both precisions: host copies
+    of every YLT and its PML/TVaR, for the CPU leg's comparison."""
+    import numpy as np
+
+    w = W.precision_poisson()
+    ids, off = W.yet_subset(w.yet, np.arange(w.yet.n_trials))
+    yet = A.yet_from_numpy(ids, off, w.yet.n_trials, w.yet.catalog_size)
+    out = {}
+    for lay_spec in w.layers:
+        for prec, layout in (("fp64", "fused"), ("fp32c", "fused"), ("fp32c", "compact")):
+            lay = A.Layer(yet, lay_spec, prec, layout)
+            y = A.run_layer(yet, lay)
+            pt = A.pml_tvar(y, list(w.return_periods))
+            out[(lay_spec.name, f"{prec}_{layout}")] = (y.cpu().numpy(), pt)
+            lay.close()
+    yet.close()
+    return w, ids, off, out
+
+
+def cpu_baseline(wl, spec, target_s, gpu_ylt=None, gpu_pml_tvar=None, rps=(), gpu_ylt32=None,
+                 gpu_pml_tvar32=None, precision=None):
     """The oracle on a bounded sample of the same workload, on the host cores;
     with the GPU's YLT of the timed pass, also the GPU's error on the sample
     (|y - y_oracle| / G per trial, G the trial's gross looked-up loss) and,
@@ -100,6 +212,7 @@ def cpu_baseline(wl, spec, target_s, gpu_ylt=None, gpu_pml_tvar=None, rps=()):
     from paper_1412_4556_amd import workloads as W
 
     threads = host_threads()
+    cpus = host_cpus()
     J = spec.n_elts
 
     def run(n, n_threads=threads):
@@ -115,7 +228,10 @@ def cpu_baseline(wl, spec, target_s, gpu_ylt=None, gpu_pml_tvar=None, rps=()):
     res = {"value": ev * J / dt, "unit": "lookups/s", "cores": threads, "kind": "oracle",
            "sample": f"first {n} of {wl.yet.n_trials} trials ({ev} trial-events x {J} ELTs), FP64, "
                      f"OpenMP over trials, {dt:.1f} s incl. direct-table build",
-           "cpu_model": cpu_model(), "seconds": dt}
+           "cpu_model": cpus["cpu_model"], "seconds": dt,
+           "host": {**cpus, "threads_used": threads,
+                    "threads_rule": "every CPU of the process's affinity, capped by OMP_NUM_THREADS when set "
+                                    "(the CPU share of one GPU on the GPU box)"}}
     # the same loop on one core (the paper's sequential form), on a smaller sample
     n1 = int(min(wl.yet.n_trials, max(100, n / threads / 4)))
     dt1, ev1, _ = run(n1, 1)
@@ -134,19 +250,22 @@ def cpu_baseline(wl, spec, target_s, gpu_ylt=None, gpu_pml_tvar=None, rps=()):
         small[w.name] = {"value": int(off[-1]) * lay.n_elts / dts, "unit": "lookups/s", "seconds": dts}
     res["single_thread_small_workloads"] = small
     if gpu_ylt is not None:
-        err = np.abs(gpu_ylt[:n] - ref["ylt"])
-        scaled = err / np.maximum(ref["gross"], 1e-300)
-        pos = ref["ylt"] > 0
-        par = {"trials_compared": n, "max_err_over_gross": float(scaled.max()),
-               "trials_over_1e-12_gross": int((err > 1e-12 * ref["gross"]).sum()),
-               "max_rel_err": float((err[pos] / ref["ylt"][pos]).max()) if pos.any() else 0.0,
-               "bitwise_equal_trials": int((gpu_ylt[:n] == ref["ylt"]).sum())}
-        if n == wl.yet.n_trials and gpu_pml_tvar is not None:
-            op, ot = oracle.pml_tvar(ref["ylt"], rps)
-            gp, gt = gpu_pml_tvar
-            par["pml_max_rel_err"] = float(np.max(np.abs(np.asarray(gp) - op) / np.abs(op)))
-            par["tvar_max_rel_err"] = float(np.max(np.abs(np.asarray(gt) - ot) / np.abs(ot)))
+        whole = n == wl.yet.n_trials
+        par = {"trials_compared": n,
+               "fp64": error_report(gpu_ylt[:n], ref, 1e-12, gpu_pml_tvar if whole else None, rps)}
+        if gpu_ylt32 is not None:
+            par["fp32c"] = error_report(gpu_ylt32[:n], ref, 1e-6, gpu_pml_tvar32 if whole else None, rps)
         res["parity"] = par
+    if precision is not None:
+        # the precision workload in full: FP64 and FP32C against the oracle
+        w, ids, off, runs = precision
+        rp = list(w.return_periods)
+        rep = {}
+        for lay_spec in w.layers:
+            ref = oracle.run_layer(ids, off, w.yet.n_trials, 0, w.yet.catalog_size, lay_spec, n_threads=threads)
+            rep[lay_spec.name] = {form: error_report(y, ref, 1e-12 if form.startswith("fp64") else 1e-6, pt, rp)
+                                  for (name, form), (y, pt) in runs.items() if name == lay_spec.name}
+        res["precision_workload"] = {"workload": w.name, "return_periods": rp, "layers": rep}
     return res
 
 
@@ -233,7 +352,7 @@ def batch_leg(A, W, torch, n_trials, steps, precision="fp64"):
     return res
 
 
-def serving_leg(A, W, torch, n_trials, rates, max_layers=128):
+def serving_leg(A, W, torch, n_trials, rates, max_layers=128, n_queries=1000, budget_s=330.0):
     """Poisson-arriving ad hoc layer queries (1..16 ELTs of a 256-ELT pool,
     random occurrence/aggregate terms) against a resident YET of Poisson(1000)
     trials: continuous batching against one query at a time."""
@@ -254,15 +373,25 @@ def serving_leg(A, W, torch, n_trials, rates, max_layers=128):
     srv.serve(S.make_queries(warm))
     S.serve_one_at_a_time(yet, P, S.make_queries(warm))
     out = []
-    for i, rate in enumerate(rates):
-        n = int(max(60, min(1000, rate * 3)))
+    t_start = time.perf_counter()
+    # fastest rates first; a rate's two runs take about 2 n / rate seconds,
+    # and a run that would not fit the time budget gets fewer queries (said
+    # in its record)
+    for i, rate in sorted(enumerate(rates), key=lambda x: -x[1]):
+        n = n_queries
+        left = budget_s - (time.perf_counter() - t_start)
+        if 2.0 * n / rate > left:
+            n = max(100, int(left * rate / 2.0))
         items = W.serving_queries(pool, n, rate, stream=i)
-        b = srv.serve(S.make_queries(items))
-        o = S.serve_one_at_a_time(yet, P, S.make_queries(items))
+        b = srv.serve(S.make_queries(items), progress=lambda k: log(f"serving {rate:.0f}/s batched: {k}/{n}"))
+        log(f"serving {rate:.0f}/s batched: done")
+        o = S.serve_one_at_a_time(yet, P, S.make_queries(items),
+                                  progress=lambda k: log(f"serving {rate:.0f}/s one at a time: {k}/{n}"))
         log(f"serving {rate:>6.0f}/s x {n}: batched p50 {b['p50_ms']:.2f} p99 {b['p99_ms']:.2f} ms "
             f"{b['layers_per_s']:.0f} layers/s (mean batch {b['mean_batch']:.1f}); one-at-a-time p50 "
             f"{o['p50_ms']:.2f} p99 {o['p99_ms']:.2f} ms {o['layers_per_s']:.0f} layers/s")
-        out.append({"rate_per_s": rate, "batched": b, "one_at_a_time": o})
+        out.append({"rate_per_s": rate, "n_queries": n, "reduced_for_time": n < n_queries, "batched": b,
+                    "one_at_a_time": o})
     res = {"workload": f"serving_{n_trials}_trials_pool_{len(pool.ids)}_elts", "n_trials": y.n_trials,
            "n_events": int(off[-1]), "pool_elts": len(pool.ids), "layer_slots": max_layers,
            "pool_device_bytes": P.device_bytes, "return_periods": [100.0, 250.0],
@@ -281,7 +410,6 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
-    ap.add_argument("--layout", default="auto", choices=["auto", "direct", "sparse", "compact", "fused"])
     ap.add_argument("--trials", type=int, default=1_000_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -291,6 +419,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-trials", type=int, default=500_000)
     ap.add_argument("--serving-rates", default="10,30,100,300,1000,3000")
+    ap.add_argument("--serving-queries", type=int, default=1000, help="queries per rate (after warm-up)")
+    ap.add_argument("--serving-budget-s", type=float, default=330.0,
+                    help="wall-clock budget of the serving sweep; slow rates past it run fewer queries")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB 5 times (counter calibration)")
     args = ap.parse_args()
@@ -327,31 +458,47 @@ def main():
     t_ids = torch.from_numpy(ids).cuda()
     del ids
     yet = A.Yet(t_ids, None, T, wl.yet.catalog_size, K)
-    # the layer's tables (for the fused layout: every event's occurrence loss
-    # and the LDS filters) are built once per layer, outside the timed step;
-    # the second build is the steady-state cost (the first one also loads code)
-    A.Layer(yet, spec, args.precision, args.layout).close()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lay = A.Layer(yet, spec, args.precision, args.layout)
-    torch.cuda.synchronize()
-    build_ms = (time.perf_counter() - t0) * 1e3
     ylt = torch.empty(T, dtype=torch.float64, device="cuda")
     rps = list(wl.return_periods)
-    log(f"layer: {J} ELTs, layout {lay.layout}, precision {lay.precision}, {lay.device_bytes} device bytes")
-
-    ms_step, k_ms, k_min, (pml, tvar) = time_layer(A, torch, yet, lay, ylt, args.steps, args.warmup, rps)
-    ylt_host = ylt.cpu().numpy()  # the timed pass's YLT, for the parity check against the oracle
     lookups = float(T) * K * J
+    # the layer's ELTs, resident in HBM like the YET (a pool of 16 ELTs)
+    pool = A.Pool(yet, spec.elt_ids, spec.elt_losses, args.precision, max_layers=2)
+    ms_step, b_ms, k_ms, k_min, (pml, tvar) = time_step(A, torch, yet, pool, spec, ylt, args.steps, args.warmup,
+                                                        rps)
+    ylt_host = ylt.cpu().numpy()  # the timed steps' YLT, for the parity check against the oracle
+    # the same layer built from host ELTs (upload over PCIe, checks, table),
+    # outside the step; the second build is the steady-state cost
+    A.Layer(yet, spec, args.precision, "fused").close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lay = A.Layer(yet, spec, args.precision, "fused")
+    torch.cuda.synchronize()
+    host_build_ms = (time.perf_counter() - t0) * 1e3
+    log(f"layer: {J} ELTs, layout {lay.layout}, precision {lay.precision}, {lay.device_bytes} device bytes")
     algo_bytes = T * K * 4 + T * 8 + lay.device_bytes
     achieved = algo_bytes / (k_ms * 1e-3) / 1e9
-    log(f"step {ms_step:.3f} ms, trial-pass kernel {k_ms:.3f} ms (min {k_min:.3f}), {achieved:.0f} GB/s")
+    log(f"step {ms_step:.3f} ms (table build {b_ms:.3f} ms, trial pass {k_ms:.3f} ms, min {k_min:.3f}), "
+        f"{achieved:.0f} GB/s; layer from host ELTs {host_build_ms:.3f} ms")
+    # the step's table is bitwise the one built from the host ELTs
+    y2 = A.run_layer(yet, lay)
+    assert torch.equal(y2, ylt), "pool-built and host-built layers differ"
+    del y2
+    # FP32C: the same step, and its YLT for the error report
+    other = "fp32c" if args.precision == "fp64" else "fp64"
+    pool2 = A.Pool(yet, spec.elt_ids, spec.elt_losses, other, max_layers=2)
+    ylt2 = torch.empty(T, dtype=torch.float64, device="cuda")
+    ms2, b2, k2, _, pt2 = time_step(A, torch, yet, pool2, spec, ylt2, args.steps, args.warmup, rps)
+    ylt2_host = ylt2.cpu().numpy()
+    log(f"{other} step {ms2:.3f} ms (table build {b2:.3f} ms, trial pass {k2:.3f} ms)")
+    pool2.close()
+    del ylt2
+    precision = precision_runs(A, W, torch) if not args.no_cpu_baseline else None
 
     extras = {}
     if not args.no_extras:
-        for prec, layout, steps in (("fp32c", args.layout, args.steps), ("fp64", "compact", 5), ("fp32c", "compact", 5),
+        for prec, layout, steps in (("fp32c", "fused", args.steps), ("fp64", "compact", 5), ("fp32c", "compact", 5),
                                     ("fp64", "direct", 3), ("fp32c", "direct", 3), ("fp64", "sparse", 2)):
-            if prec == args.precision and layout == args.layout:
+            if prec == args.precision and layout == "fused":
                 continue
             l2 = A.Layer(yet, spec, prec, layout)
             s2, k2, _, _ = time_layer(A, torch, yet, l2, ylt, steps, 1, rps, with_pml=False)
@@ -409,6 +556,7 @@ def main():
 
     lay_layout, lay_prec = lay.layout, lay.precision
     del t_ids
+    pool.close()
     yet.close()
     lay.close()
     torch.cuda.empty_cache()
@@ -419,12 +567,16 @@ def main():
     serving = None
     if not args.no_serving:
         serving = serving_leg(A, W, torch, args.serving_trials,
-                              [float(r) for r in args.serving_rates.split(",") if r])
+                              [float(r) for r in args.serving_rates.split(",") if r],
+                              n_queries=args.serving_queries, budget_s=args.serving_budget_s)
 
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(wl, spec, args.cpu_seconds, gpu_ylt=ylt_host, gpu_pml_tvar=(pml, tvar), rps=rps)
+        y64, y32 = (ylt_host, ylt2_host) if args.precision == "fp64" else (ylt2_host, ylt_host)
+        p64, p32 = ((pml, tvar), pt2) if args.precision == "fp64" else (pt2, (pml, tvar))
+        cpu = cpu_baseline(wl, spec, args.cpu_seconds, gpu_ylt=y64, gpu_pml_tvar=p64, rps=rps, gpu_ylt32=y32,
+                           gpu_pml_tvar32=p32, precision=precision)
         log(f"cpu baseline {cpu['value']:.3e} lookups/s on {cpu['cores']} threads")
 
     rec = {
@@ -444,11 +596,15 @@ def main():
                    "elts": J, "elt_size": 20_000, "layout": lay_layout, "precision": lay_prec,
                    "return_periods": rps},
         "trial_events_per_s": T * K / (ms_step * 1e-3),
-        "lookups_are": ("equivalent: the fused layout adds the J ELTs' losses of each catalogue event once per "
-                        "layer (layer_build_ms) and looks each trial-event up once"
-                        if lay_layout == "fused" else "J ELT lookups per trial-event"),
-        "layer_build_ms": build_ms,
-        "value_incl_layer_build": lookups / ((ms_step + build_ms) * 1e-3),
+        "lookups_are": ("equivalent: each step builds the layer's fused table from its device-resident ELTs "
+                        "(the J ELT losses of every catalogue event through FT1, summed, through FT2) and the "
+                        "trial pass reads one entry per trial-event"),
+        "step_parts_ms": {"table_build_from_device_elts": b_ms, "trial_pass": k_ms,
+                          "pml_tvar_and_host_overheads": ms_step - b_ms - k_ms},
+        "layer_build_from_host_elts_ms": host_build_ms,
+        "value_with_host_elt_build": lookups / ((ms_step - b_ms + host_build_ms) * 1e-3),
+        "other_precision_step": {"precision": other, "ms_per_step": ms2, "value": lookups / (ms2 * 1e-3),
+                                 "table_build_ms": b2, "trial_pass_ms": k2},
         "kernel_ms": k_ms,
         "hbm_gbps_algorithmic": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",

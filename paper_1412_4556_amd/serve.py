@@ -109,7 +109,9 @@ class BatchingServer:
                 b.close()
         self.batches = [None, None]
 
-    def serve(self, queries: Sequence[Query], keep_ylt: bool = False) -> dict:
+    def serve(self, queries: Sequence[Query], keep_ylt: bool = False, progress=None) -> dict:
+        """Serve the queries at their arrival times; ``progress(n_done)`` (if
+        given) is called each time another 200 answers are out."""
         yet, pool = self.yet, self.pool
         run_s, build_s, answer_s = self.run_s, self.build_s, self.answer_s
         T = yet.n_trials
@@ -122,7 +124,11 @@ class BatchingServer:
         n_launches = 0
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0
+        reported = 0
         while n_done < len(queries):
+            if progress is not None and n_done - reported >= 200:
+                reported = n_done - n_done % 200
+                progress(n_done)
             now = clock()
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
@@ -198,22 +204,25 @@ class BatchingServer:
 
 
 def serve_batched(yet: A.Yet, pool: A.Pool, queries: Sequence[Query], return_periods=(100.0, 250.0),
-                  max_batch: int = L.ARA_MAX_BATCH, min_batch: int = 2, keep_ylt: bool = False) -> dict:
+                  max_batch: int = L.ARA_MAX_BATCH, min_batch: int = 2, keep_ylt: bool = False,
+                  progress=None) -> dict:
     """One run of a fresh BatchingServer."""
     srv = BatchingServer(yet, pool, return_periods, max_batch, min_batch)
     try:
-        return srv.serve(queries, keep_ylt)
+        return srv.serve(queries, keep_ylt, progress)
     finally:
         srv.close()
 
 
 def serve_one_at_a_time(yet: A.Yet, pool: A.Pool, queries: Sequence[Query], return_periods=(100.0, 250.0),
-                        keep_ylt: bool = False) -> dict:
+                        keep_ylt: bool = False, progress=None) -> dict:
     s = torch.cuda.Stream()
     T = yet.n_trials
     t0 = time.perf_counter()
     clock = lambda: time.perf_counter() - t0
-    for q in sorted(queries, key=lambda q: q.arrival):
+    for i, q in enumerate(sorted(queries, key=lambda q: q.arrival)):
+        if progress is not None and i and i % 200 == 0:
+            progress(i)
         _wait_until(clock, q.arrival)
         q.admitted = clock()
         lay = _build(pool, q, s)

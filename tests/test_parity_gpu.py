@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_cases import TOL, assert_close_to_oracle, gpu_layer_run, oracle_run
+from gpu_cases import TOL, assert_close_to_oracle, assert_risk_close, gpu_layer_run, oracle_run
 from oracle import oracle
 from paper_1412_4556_amd import _lib as L
 from paper_1412_4556_amd import ara as A
@@ -102,24 +102,23 @@ def test_plain_tiny_all_layouts(tiny):
     assert np.array_equal(gp, op)
     assert np.allclose(gt, ot, rtol=1e-12, atol=0)
     rp, rt = oracle.pml_tvar(ref["ylt"], wl.return_periods)
-    bound = TOL["fp64"] * ref["gross"].max()
-    assert np.all(np.abs(gp - rp) <= bound) and np.all(np.abs(gt - rt) <= bound)
+    assert_risk_close(gp, gt, rp, rt, "fp64", ref)
 
 
+@pytest.mark.parametrize("layout", ["fused", "compact"])
 @pytest.mark.parametrize("prec", PRECS)
-def test_precision_workload(prec):
+def test_precision_workload(prec, layout):
     wl = W.precision_poisson()
     ids, off = W.yet_full(wl.yet)
     T, C = wl.yet.n_trials, wl.yet.catalog_size
     for spec in wl.layers:
         ref = oracle_run(ids, off, T, C, 0, spec)
-        y = gpu_layer_run(ids, off, T, C, 0, spec, prec, "compact")
+        y = gpu_layer_run(ids, off, T, C, 0, spec, prec, layout)
         stats = assert_close_to_oracle(y, ref, prec)
         gp, gt = A.pml_tvar(torch.from_numpy(y).cuda(), wl.return_periods)
         rp, rt = oracle.pml_tvar(ref["ylt"], wl.return_periods)
-        bound = TOL[prec] * ref["gross"].max()
-        assert np.all(np.abs(gp - rp) <= bound) and np.all(np.abs(gt - rt) <= bound)
-        print(spec.name, prec, stats, "pml rel err", np.abs(gp - rp) / rp, "tvar rel err", np.abs(gt - rt) / rt)
+        risk = assert_risk_close(gp, gt, rp, rt, prec, ref)
+        print(spec.name, prec, layout, stats, risk)
         if spec.name == "pareto_uncapped_elt":
             assert (ref["ylt"] > 0).mean() > 0.01
 

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_cases import assert_close_to_oracle, oracle_run
+from gpu_cases import assert_close_to_oracle, assert_risk_close, oracle_run
 from oracle import oracle
 from paper_1412_4556_amd import _lib as L
 from paper_1412_4556_amd import ara as A
@@ -112,8 +112,7 @@ def test_served_answers_same_alone_and_in_mix(prec, max_layers):
         ref = oracle_run(ids, off, T, C, 0, spec)
         assert_close_to_oracle(q.ylt.cpu().numpy(), ref, prec)
         rp, rt = oracle.pml_tvar(ref["ylt"], RPS)
-        tol = (1e-12 if prec == "fp64" else 1e-6) * ref["gross"].max()
-        assert np.all(np.abs(q.pml - rp) <= tol) and np.all(np.abs(q.tvar - rt) <= tol)
+        assert_risk_close(q.pml, q.tvar, rp, rt, prec, ref)
 
 
 def test_pml_tvar_many_matches_single():
