@@ -176,11 +176,16 @@ ara_status ara_run_layer_max_occurrence(ara_yet yet, ara_layer layer, double *d_
 /* Several layers over one YET in one pass (Algorithm 1's loop over the
  * layers of a program, with the YET read once for all of them).
  *
- * A batch holds, for every catalogue event, one 64-byte (FP64) or 32-byte
- * (FP32C) record of the layers in which its occurrence loss is non-zero and
- * those losses; the trial pass reads one record per trial-event and keeps one
- * running sum per (layer, lane), adding each layer's losses in the same order
- * as the single-layer pass.
+ * A batch of up to 16 layers holds, per group of at most 4 of its layers
+ * and per catalogue event, one dense record of the event's occurrence losses
+ * in those layers, and LDS filters of the events with any non-zero loss:
+ * one pass over the YET per group of 4 layers, gathering a record only for
+ * events that pass the filters.  A larger batch holds one 64-byte (FP64) or
+ * 32-byte (FP32C) record per catalogue event of the layers in which its
+ * occurrence loss is non-zero and those losses, and reads one record per
+ * trial-event in a single pass.  Either way the pass keeps one running sum
+ * per (layer, lane), adding each layer's losses in the same order as the
+ * single-layer pass.
  *   layers    1 .. ARA_MAX_BATCH layer handles, all built against this YET
  *             with ARA_LAYOUT_FUSED (or AUTO) and the same precision
  *             (else ARA_ERR_UNSUPPORTED / ARA_ERR_INVALID_ARG).  The batch
@@ -205,7 +210,9 @@ size_t ara_batch_device_bytes(ara_batch batch);
  * rebuild that moved them); once rebuilt with another number of layers, the
  * batch launches its pass directly instead (a server's batches change size
  * all the time).  A run queued on another stream than the batch's previous
- * run waits for that run. */
+ * run waits for that run.  After a failed rebuild the batch holds no valid
+ * records: ara_run_batch returns ARA_ERR_INVALID_ARG until a rebuild
+ * succeeds. */
 ara_status ara_batch_rebuild(ara_batch batch, const ara_layer *layers, int32_t n_layers);
 /* Launch shape chosen for the batch (0, 0 before its first run). */
 ara_status ara_batch_launch_config(ara_batch batch, int32_t *threads, int32_t *wg_per_cu);
@@ -275,7 +282,7 @@ ara_status ara_pml_tvar_many(const double *const *d_ylts, int32_t n_ylts, int64_
  * memory or wait for the device (code being captured into a HIP graph, tight
  * serving loops, harnesses that forbid hipMalloc): the same kernels and the
  * same results, bitwise, but every scratch buffer lives in a static device
- * array of the library (about 1 MiB per GPU, held until the process ends)
+ * array of the library (about 2 MiB per GPU, held until the process ends)
  * and the results stay on the device.
  *   d_ylts, n_ylts, n_trials, h_return_periods, n_rp   as ara_pml_tvar_many,
  *               with n_ylts * n_rp <= ARA_NOALLOC_MAX_SEL (else
@@ -288,9 +295,11 @@ ara_status ara_pml_tvar_many(const double *const *d_ylts, int32_t n_ylts, int64_
  * no synchronisation.  Every call on one GPU uses the same scratch: calls
  * whose work overlaps on the device (e.g. queued on two streams without an
  * order between them) race and give undefined results; calls ordered on one
- * stream are safe (each starts by clearing what it needs at zero).  Errors:
- * as ara_pml_tvar_many, detected on the host before any launch. */
-#define ARA_NOALLOC_MAX_SEL 64
+ * stream are safe: a call that runs to its end leaves the scratch's flags
+ * and histograms at zero for the next one (the first call on a device, and
+ * a call after one that failed between its launches, clears them first).
+ * Errors: as ara_pml_tvar_many, detected on the host before any launch. */
+#define ARA_NOALLOC_MAX_SEL 128
 ara_status ara_pml_tvar_many_noalloc(const double *const *d_ylts, int32_t n_ylts, int64_t n_trials,
                                      const double *h_return_periods, int32_t n_rp, double *d_pml, double *d_tvar,
                                      void *hip_stream);

@@ -26,7 +26,7 @@ ARA_FP64, ARA_FP32C = 0, 1
 ARA_LAYOUT_AUTO, ARA_LAYOUT_DIRECT, ARA_LAYOUT_SPARSE, ARA_LAYOUT_COMPACT, ARA_LAYOUT_FUSED = 0, 1, 2, 3, 4
 ARA_MAX_ELTS = 32
 ARA_MAX_BATCH = 64
-ARA_NOALLOC_MAX_SEL = 64
+ARA_NOALLOC_MAX_SEL = 128
 
 _P = ctypes.c_void_p
 _I32, _I64, _D, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t

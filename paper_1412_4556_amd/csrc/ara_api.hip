@@ -62,14 +62,24 @@ struct ara_batch_s {
     int32_t n = 0;
     int32_t precision = 0;
     int32_t catalog = 0;
-    void *d_rec = nullptr;
+    // form of the current layers: dense (at most ara::kDenseMax layers) or
+    // sparse records; each form's buffers are allocated when first needed
+    // and kept (grown, never shrunk) for later rebuilds
+    bool dense = false;
+    void *d_dense = nullptr;      // dense records: sub-table s at s * dense_stride bytes
+    size_t dense_cap = 0;         // bytes
+    size_t dense_stride = 0;      // bytes of one sub-table ((catalog + 1) * kDenseWidth values)
+    uint32_t *d_dfilt = nullptr;  // dense filters: sub-table s at s * (n_fwords + n_hwords) words
+    int32_t dfilt_subs = 0;       // sub-tables the filter allocation holds
+    int32_t fshift = 0, n_fwords = 0, n_hwords = 0, hshift = 0;
+    void *d_rec = nullptr;        // sparse records
     void *d_ovf_lid = nullptr;
     void *d_ovf_val = nullptr;
-    double **d_ylts = nullptr;  // device array of the YLT pointers of the last run
-    double *d_agg = nullptr;    // [2 * ARA_MAX_BATCH]: aggregate retentions, then limits
     int32_t *d_count = nullptr; // [catalog] entries per event (record build scratch)
     unsigned long long *d_ctr = nullptr;  // overflow total, fill cursor
     unsigned long long ovf_cap = 0;
+    double **d_ylts = nullptr;  // device array of the YLT pointers of the last run
+    double *d_agg = nullptr;    // [2 * ARA_MAX_BATCH]: aggregate retentions, then limits
     std::vector<double *> h_ylts;
     ara::BatchLaunch cfg{256, 1};
     bool tuned = false;
@@ -77,8 +87,11 @@ struct ara_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     // what the captured graph's kernel arguments hold: it is replayed only
-    // while the batch's tables and launch shape are still these
+    // while the batch's form, tables and launch shape are still these
+    bool graph_dense = false;
     ara::BatchTables graph_tables{};
+    const void *graph_drec = nullptr;
+    const uint32_t *graph_dfilt = nullptr;
     ara::BatchLaunch graph_cfg{0, 0};
     // recorded on the caller's stream after every run: a rebuild, and a run
     // on another stream, wait for it before they overwrite what the last
@@ -86,6 +99,7 @@ struct ara_batch_s {
     hipEvent_t last_run = nullptr;
     hipStream_t last_stream = nullptr;
     bool ran = false;
+    bool valid = false;  // records match the layers (false after a failed rebuild)
     size_t bytes = 0;
     int device = 0;
 };
@@ -808,7 +822,7 @@ static void free_batch(ara_batch b) {
     drop_graph(b);
     if (b->last_run) (void)hipEventDestroy(b->last_run);
     for (void *p : {b->d_rec, b->d_ovf_lid, b->d_ovf_val, (void *)b->d_ylts, (void *)b->d_agg, (void *)b->d_count,
-                     (void *)b->d_ctr})
+                     (void *)b->d_ctr, b->d_dense, (void *)b->d_dfilt})
         if (p) (void)hipFree(p);
     delete b;
 }
@@ -830,23 +844,107 @@ static ara_status check_batch_layers(int32_t catalog, const ara_layer *layers, i
     return ARA_OK;
 }
 
-ara_status ara_batch_rebuild(ara_batch b, const ara_layer *layers, int32_t n_layers) {
-    if (!b) return fail(ARA_ERR_INVALID_ARG, "NULL batch");
-    const void *occ[ARA_MAX_BATCH];
-    int32_t prec = b->precision;
-    ara_status st = check_batch_layers(b->catalog, layers, n_layers, &prec, occ);
-    if (st != ARA_OK) return st;
-    const bool fp64 = prec == ARA_FP64;
+namespace {
+
+// Sub-tables of the dense form: sub-table s takes layers
+// [kDenseWidth s, kDenseWidth s + width), records of the next power of two
+// of its width.
+int dense_subs(int32_t n) { return (n + ara::kDenseWidth - 1) / ara::kDenseWidth; }
+
+ara::DenseTables dense_tables(ara_batch b, int sub) {
+    const int first = sub * ara::kDenseWidth;
+    const int cnt = b->n - first < ara::kDenseWidth ? b->n - first : ara::kDenseWidth;
+    int nl = 1;
+    while (nl < cnt) nl <<= 1;
+    ara::DenseTables t{};
+    t.rec = static_cast<const char *>(b->d_dense) + (size_t)sub * b->dense_stride;
+    t.filt = b->d_dfilt + (size_t)sub * (size_t)(b->n_fwords + b->n_hwords);
+    t.n_fwords = b->n_fwords;
+    t.fshift = b->fshift;
+    t.n_hwords = b->n_hwords;
+    t.hshift = b->hshift;
+    t.catalog = b->catalog;
+    t.nl = nl;
+    t.ylts = b->d_ylts + first;
+    t.agg_ret = b->d_agg + first;
+    t.agg_lim = b->d_agg + ARA_MAX_BATCH + first;
+    t.n_layers = cnt;
+    return t;
+}
+
+// Dense records and filters of up to ara::kDenseMax layers (on s, after the
+// waits the caller queued).  Sets b->n to n_layers (the sub-table geometry
+// follows from it).
+ara_status rebuild_dense(ara_batch b, const void *const *occ, int32_t n_layers, bool fp64, hipStream_t s) {
+    const int subs = dense_subs(n_layers);
     const size_t val_bytes = fp64 ? 8 : 4;
-    hipStream_t s = ara::internal_stream();
-    if (!s) return fail(ARA_ERR_DEVICE, "no set-up stream");
+    const size_t stride = (((size_t)b->catalog + 1) * ara::kDenseWidth * val_bytes + 255) & ~(size_t)255;
+    const size_t need = stride * (size_t)subs;
+    const size_t fwords = (size_t)(b->n_fwords + b->n_hwords);
     hipError_t e = hipSuccess;
-    // everything below overwrites what the batch's last run reads: wait for it
-    if (b->ran) e = hipStreamWaitEvent(s, b->last_run, 0);
-    for (int l = 0; l < n_layers && e == hipSuccess; ++l)
-        if (layers[l]->ready) e = hipStreamWaitEvent(s, layers[l]->ready, 0);
+    if (need > b->dense_cap || subs > b->dfilt_subs) {
+        // grows only; the wait for the last run is queued on s, so finish it
+        // before the frees
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "waiting for the batch's last run");
+    }
+    if (subs > b->dfilt_subs) {
+        if (b->d_dfilt) (void)hipFree(b->d_dfilt);
+        b->bytes -= (size_t)b->dfilt_subs * fwords * sizeof(uint32_t);
+        b->d_dfilt = nullptr;
+        b->dfilt_subs = 0;
+        e = dev_alloc(reinterpret_cast<void **>(&b->d_dfilt), (size_t)subs * fwords * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            b->d_dfilt = nullptr;
+            return hip_fail(e, "batch filter allocation");
+        }
+        b->dfilt_subs = subs;
+        b->bytes += (size_t)subs * fwords * sizeof(uint32_t);
+    }
+    if (need > b->dense_cap) {
+        if (b->d_dense) (void)hipFree(b->d_dense);
+        b->bytes -= b->dense_cap;
+        b->d_dense = nullptr;
+        b->dense_cap = 0;
+        e = dev_alloc(&b->d_dense, need);
+        if (e != hipSuccess) {
+            b->d_dense = nullptr;
+            return hip_fail(e, "batch record allocation");
+        }
+        b->dense_cap = need;
+        b->bytes += need;
+    }
+    b->dense_stride = stride;
+    b->n = n_layers;
+    for (int sub = 0; sub < subs && e == hipSuccess; ++sub) {
+        const ara::DenseTables t = dense_tables(b, sub);
+        e = ara::launch_dense_fill(occ + sub * ara::kDenseWidth, t.n_layers, fp64, t, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "building the batch records");
+    return ARA_OK;
+}
+
+// Sparse records (on s, after the waits the caller queued).
+ara_status rebuild_sparse(ara_batch b, const void *const *occ, int32_t n_layers, bool fp64, hipStream_t s) {
+    const size_t val_bytes = fp64 ? 8 : 4;
+    const size_t C = (size_t)b->catalog;
+    hipError_t e = hipSuccess;
+    if (!b->d_rec) {
+        const size_t rec_bytes = fp64 ? 64 : 32;
+        e = dev_alloc(&b->d_rec, C * rec_bytes);
+        if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_count), C * sizeof(int32_t));
+        if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_ctr), 2 * sizeof(unsigned long long));
+        if (e != hipSuccess) {
+            for (void **p : {&b->d_rec, reinterpret_cast<void **>(&b->d_count), reinterpret_cast<void **>(&b->d_ctr)}) {
+                if (*p) (void)hipFree(*p);
+                *p = nullptr;
+            }
+            return hip_fail(e, "batch record allocation");
+        }
+        b->bytes += C * (rec_bytes + sizeof(int32_t)) + 16;
+    }
     unsigned long long h_ctr[2] = {0, 0};
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_ctr, h_ctr, sizeof(h_ctr), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(b->d_ctr, h_ctr, sizeof(h_ctr), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = ara::launch_batch_count(occ, n_layers, b->catalog, fp64, b->d_count, b->d_ctr, s);
     if (e == hipSuccess) e = hipMemcpyAsync(h_ctr, b->d_ctr, sizeof(h_ctr), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -856,7 +954,7 @@ ara_status ara_batch_rebuild(ara_batch b, const ara_layer *layers, int32_t n_lay
     const unsigned long long n_ovf = h_ctr[0] > 0 ? h_ctr[0] : 1;
     if (n_ovf >= (1ULL << 32)) return fail(ARA_ERR_UNSUPPORTED, "too many overflow entries for one batch");
     if (n_ovf > b->ovf_cap) {
-        // grows only; freeing waits for the device
+        // grows only; the stream is idle here, the last run finished
         if (b->d_ovf_lid) (void)hipFree(b->d_ovf_lid);
         if (b->d_ovf_val) (void)hipFree(b->d_ovf_val);
         b->d_ovf_lid = b->d_ovf_val = nullptr;
@@ -868,26 +966,53 @@ ara_status ara_batch_rebuild(ara_batch b, const ara_layer *layers, int32_t n_lay
         b->ovf_cap = n_ovf;
         b->bytes += (size_t)n_ovf * (1 + val_bytes);
     }
+    e = ara::launch_batch_fill(occ, n_layers, b->catalog, fp64, b->d_count, b->d_rec,
+                               static_cast<uint8_t *>(b->d_ovf_lid), b->d_ovf_val, b->d_ctr + 1, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "building the batch records");
+    return ARA_OK;
+}
+
+}  // namespace
+
+ara_status ara_batch_rebuild(ara_batch b, const ara_layer *layers, int32_t n_layers) {
+    if (!b) return fail(ARA_ERR_INVALID_ARG, "NULL batch");
+    const void *occ[ARA_MAX_BATCH];
+    int32_t prec = b->precision;
+    ara_status st = check_batch_layers(b->catalog, layers, n_layers, &prec, occ);
+    if (st != ARA_OK) return st;
+    const bool fp64 = prec == ARA_FP64;
+    hipStream_t s = ara::internal_stream();
+    if (!s) return fail(ARA_ERR_DEVICE, "no set-up stream");
+    hipError_t e = hipSuccess;
+    // everything below overwrites what the batch's last run reads: wait for it
+    if (b->ran) e = hipStreamWaitEvent(s, b->last_run, 0);
+    for (int l = 0; l < n_layers && e == hipSuccess; ++l)
+        if (layers[l]->ready) e = hipStreamWaitEvent(s, layers[l]->ready, 0);
     std::vector<double> agg(2 * ARA_MAX_BATCH, 0.0);
     for (int l = 0; l < n_layers; ++l) {
         agg[l] = layers[l]->h.t64.agg_ret;
         agg[ARA_MAX_BATCH + l] = layers[l]->h.t64.agg_lim;
     }
-    e = hipMemcpyAsync(b->d_agg, agg.data(), sizeof(double) * agg.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = ara::launch_batch_fill(occ, n_layers, b->catalog, fp64, b->d_count, b->d_rec,
-                                   static_cast<uint8_t *>(b->d_ovf_lid), b->d_ovf_val, b->d_ctr + 1, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "building the batch records");
-    if (n_layers != b->n) {
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_agg, agg.data(), sizeof(double) * agg.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "batch terms");
+    const bool dense = n_layers <= ara::kDenseMax;
+    const int32_t n_before = b->n;
+    b->valid = false;
+    st = dense ? rebuild_dense(b, occ, n_layers, fp64, s) : rebuild_sparse(b, occ, n_layers, fp64, s);
+    b->n = n_before;
+    if (st != ARA_OK) return st;
+    if (n_layers != b->n || dense != b->dense) {
         // a batch whose size changes (a server's) launches directly from now
         // on instead of capturing a graph per size
         drop_graph(b);
         b->tuned = false;
         b->use_graph = b->n == 0;
         b->n = n_layers;
+        b->dense = dense;
     }
     b->h_ylts.assign(n_layers, nullptr);
+    b->valid = true;
     return ARA_OK;
 }
 
@@ -905,20 +1030,16 @@ ara_status ara_create_batch(ara_yet yet, const ara_layer *layers, int32_t n_laye
     b->precision = prec;
     b->catalog = yet->catalog;
     (void)hipGetDevice(&b->device);
-    const size_t C = (size_t)yet->catalog;
-    const size_t rec_bytes = prec == ARA_FP64 ? 64 : 32;
+    filter_geometry(yet->catalog, b->fshift, b->n_fwords, b->n_hwords, b->hshift);
     hipError_t e = hipEventCreateWithFlags(&b->last_run, hipEventDisableTiming);
     if (e != hipSuccess) b->last_run = nullptr;
-    if (e == hipSuccess) e = dev_alloc(&b->d_rec, C * rec_bytes);
-    if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_count), C * sizeof(int32_t));
-    if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_ctr), 2 * sizeof(unsigned long long));
     if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_ylts), sizeof(double *) * ARA_MAX_BATCH);
     if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_agg), sizeof(double) * 2 * ARA_MAX_BATCH);
     if (e != hipSuccess) {
         free_batch(b);
         return hip_fail(e, "batch allocation");
     }
-    b->bytes = C * (rec_bytes + sizeof(int32_t)) + 16 + (sizeof(double *) + 2 * sizeof(double)) * ARA_MAX_BATCH;
+    b->bytes = (sizeof(double *) + 2 * sizeof(double)) * ARA_MAX_BATCH;
     st = ara_batch_rebuild(b, layers, n_layers);
     if (st != ARA_OK) {
         free_batch(b);
@@ -1015,20 +1136,35 @@ hipError_t tune_batch(ara_batch b, hipStream_t s) {
     return hipSuccess;
 }
 
+// One launch of the batch's pass in its current form.
+hipError_t pass_once(ara_batch b, hipStream_t s) {
+    const bool fp64 = b->precision == ARA_FP64;
+    if (b->dense) {
+        hipError_t e = hipSuccess;
+        for (int sub = 0; sub < dense_subs(b->n) && e == hipSuccess; ++sub)
+            e = ara::launch_dense_pass(b->yv, dense_tables(b, sub), fp64, s);
+        return e;
+    }
+    return ara::launch_batch_pass(b->yv, batch_tables(b), fp64, b->cfg, s);
+}
+
 hipError_t capture_batch(ara_batch b) {
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = ara::launch_batch_pass(b->yv, batch_tables(b), b->precision == ARA_FP64, b->cfg, cs);
+        hipError_t le = pass_once(b, cs);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cs, &g);
         if (e == hipSuccess) e = le;
         if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
         if (e == hipSuccess) {
             b->graph = g;
+            b->graph_dense = b->dense;
             b->graph_tables = batch_tables(b);
+            b->graph_drec = b->d_dense;
+            b->graph_dfilt = b->d_dfilt;
             b->graph_cfg = b->cfg;
         } else {
             b->exec = nullptr;
@@ -1043,9 +1179,12 @@ hipError_t capture_batch(ara_batch b) {
 // shape as kernel arguments; a rebuild may have reallocated the overflow
 // arrays, so the graph is replayed only while they are unchanged.
 bool graph_current(const ara_batch b) {
+    if (!b->exec || b->dense != b->graph_dense) return false;
+    if (b->dense)  // the layer count is the graph's whenever the graph exists
+        return b->d_dense == b->graph_drec && b->d_dfilt == b->graph_dfilt && b->n == b->graph_tables.n_layers;
     const ara::BatchTables now = batch_tables(b);
     const ara::BatchTables &was = b->graph_tables;
-    return b->exec && now.rec == was.rec && now.ovf_lid == was.ovf_lid && now.ovf_val == was.ovf_val &&
+    return now.rec == was.rec && now.ovf_lid == was.ovf_lid && now.ovf_val == was.ovf_val &&
            now.ylts == was.ylts && now.agg_ret == was.agg_ret && now.agg_lim == was.agg_lim &&
            now.n_layers == was.n_layers && b->cfg.threads == b->graph_cfg.threads &&
            b->cfg.wg_per_cu == b->graph_cfg.wg_per_cu;
@@ -1056,7 +1195,7 @@ bool graph_current(const ara_batch b) {
 ara_status launch_batch(ara_batch batch, hipStream_t s) {
     hipError_t e = hipSuccess;
     if (!batch->use_graph) {
-        e = ara::launch_batch_pass(batch->yv, batch_tables(batch), batch->precision == ARA_FP64, batch->cfg, s);
+        e = pass_once(batch, s);
         if (e != hipSuccess) return hip_fail(e, "batch launch");
     } else {
         if (batch->exec && !graph_current(batch)) drop_graph(batch);
@@ -1074,6 +1213,7 @@ ara_status launch_batch(ara_batch batch, hipStream_t s) {
 
 ara_status ara_run_batch(ara_batch batch, double *const *d_ylts, void *hip_stream) {
     if (!batch || !d_ylts) return fail(ARA_ERR_INVALID_ARG, "NULL batch or d_ylts");
+    if (!batch->valid) return fail(ARA_ERR_INVALID_ARG, "the batch's last rebuild failed; rebuild it first");
     for (int l = 0; l < batch->n; ++l)
         if (!d_ylts[l] && batch->yv.n_trials > 0) return fail(ARA_ERR_INVALID_ARG, "NULL YLT pointer");
     if (batch->yv.n_trials == 0) return ARA_OK;
@@ -1098,7 +1238,7 @@ ara_status ara_run_batch(ara_batch batch, double *const *d_ylts, void *hip_strea
             e = ara::launch_fill_zero(d_ylts[l], batch->yv.n_trials, s);
         if (e != hipSuccess) return hip_fail(e, "zero YLTs");
     } else {
-        if (!batch->tuned) {
+        if (!batch->tuned && !batch->dense) {
             e = tune_batch(batch, s);
             if (e != hipSuccess) return hip_fail(e, "batch launch tuning");
         }
@@ -1114,6 +1254,12 @@ ara_status ara_run_batch(ara_batch batch, double *const *d_ylts, void *hip_strea
 
 ara_status ara_batch_launch_config(ara_batch batch, int32_t *threads, int32_t *wg_per_cu) {
     if (!batch || !threads || !wg_per_cu) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    if (batch->dense) {
+        // fixed shape: 1024-thread groups, the LDS filters allow one per CU
+        *threads = batch->ran ? 1024 : 0;
+        *wg_per_cu = batch->ran ? 1 : 0;
+        return ARA_OK;
+    }
     *threads = batch->tuned ? batch->cfg.threads : 0;
     *wg_per_cu = batch->tuned ? batch->cfg.wg_per_cu : 0;
     return ARA_OK;

@@ -140,6 +140,30 @@ struct BatchTables {
     int32_t n_layers;
 };
 
+// Dense form of a batch of at most kDenseMax layers, in sub-tables of at
+// most kDenseWidth layers each (one pass over the YET per sub-table).  A
+// sub-table holds one record of nl values per catalogue event (its
+// occurrence losses in the sub-table's layers, in layer order, zeros past
+// n_layers; the record of event `catalog` is all zeros), event-major, and
+// the fused layers' two LDS filters built over the events with any non-zero
+// value (same geometry as a fused layer's).
+constexpr int kDenseMax = 16;
+constexpr int kDenseWidth = 4;
+struct DenseTables {
+    const void *rec;          // [(catalog + 1) * nl]
+    const uint32_t *filt;     // [n_fwords + n_hwords]
+    int32_t n_fwords;
+    int32_t fshift;
+    int32_t n_hwords;
+    int32_t hshift;
+    int32_t catalog;
+    int32_t nl;               // record width: 1, 2 or 4
+    double *const *ylts;      // device array [n_layers] of YLT pointers
+    const double *agg_ret;    // [n_layers]
+    const double *agg_lim;    // [n_layers]
+    int32_t n_layers;
+};
+
 struct BatchLaunch {
     int threads;     // work-group size (multiple of 64)
     int wg_per_cu;   // work-groups per CU requested (clamped by LDS)
@@ -153,6 +177,10 @@ hipError_t launch_batch_fill(const void *const *occ, int32_t n_layers, int32_t c
                              const int32_t *d_count, void *d_rec, uint8_t *d_ovf_lid, void *d_ovf_val,
                              unsigned long long *d_ovf_cursor, hipStream_t s);
 hipError_t launch_batch_pass(const YetView &y, const BatchTables &b, bool fp64, const BatchLaunch &cfg, hipStream_t s);
+// Dense form: records and filters from the layers' fused tables (filter
+// words cleared first), then the pass.
+hipError_t launch_dense_fill(const void *const *occ, int32_t n_layers, bool fp64, const DenseTables &d, hipStream_t s);
+hipError_t launch_dense_pass(const YetView &y, const DenseTables &d, bool fp64, hipStream_t s);
 size_t batch_lds_bytes(int32_t n_layers, int threads);
 // Fused table of a layer, built on the GPU: the ELTs idx[0..n) of device
 // arrays d_ids / d_loss (ELT k at host offsets off[k] .. off[k + 1]) added

@@ -961,6 +961,170 @@ __global__ __launch_bounds__(512) void k_trial_pass_batch(YetView y, const int64
 }
 
 // --------------------------------------------------------------------------------------------
+// dense batched pass: at most kDenseWidth layers per pass, one record of
+// all their occurrence losses per event, the union of their non-zero events
+// as LDS filters
+
+template <typename T, int NL>
+struct alignas(sizeof(T) * NL <= 16 ? sizeof(T) * NL : 16) DenseRec {
+    T v[NL];
+};
+
+// Records and filters of the dense form.  A wave takes 64 consecutive
+// events: every lane writes its event's record, the lanes' block-filter
+// bits are OR-ed over the wave per filter word (a wave's events fall into
+// one word, or two when blocks are single events) and set with one atomic
+// OR per word; the hashed filter gets one atomic OR per non-zero event.
+// Filter words are cleared beforehand.
+template <typename T, int NL>
+__global__ __launch_bounds__(256) void k_dense_fill(OccPtrs occ, int32_t n_layers, int32_t catalog,
+                                                    DenseRec<T, NL> *__restrict__ rec, uint32_t *__restrict__ filt,
+                                                    int32_t fshift, uint32_t *__restrict__ hwords, int32_t n_hwords,
+                                                    int32_t hshift) {
+    const int lane = lane_id();
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    for (int64_t base = wave * kWave; base <= (int64_t)catalog; base += n_waves * kWave) {
+        const int64_t e = base + lane;
+        DenseRec<T, NL> r;
+        uint32_t any = 0;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const T v = (l < n_layers && e < catalog) ? static_cast<const T *>(occ.p[l])[e] : T(0);
+            r.v[l] = v;
+            any |= v != T(0) ? 1u : 0u;
+        }
+        if (e <= catalog) rec[e] = r;
+        const int64_t blk = e >> fshift;
+        const int64_t w = blk >> 5;
+        const int64_t w_first = (base >> fshift) >> 5;
+        const uint32_t bit = any ? 1u << (uint32_t)(blk & 31) : 0u;
+        uint32_t lo = w == w_first ? bit : 0u, hi = w == w_first ? 0u : bit;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            lo |= (uint32_t)__shfl_xor((int)lo, m, kWave);
+            hi |= (uint32_t)__shfl_xor((int)hi, m, kWave);
+        }
+        if (lane == 0 && lo) atomicOr(&filt[w_first], lo);
+        if (lane == 0 && hi) atomicOr(&filt[w_first + 1], hi);
+        if (n_hwords > 0 && any) {
+            const uint32_t h = hash_slot((uint32_t)e, hshift);
+            atomicOr(&hwords[h >> 5], 1u << (h & 31u));
+        }
+    }
+}
+
+// LDS filter probes of a group: the record index of every event, that of
+// the all-zero record for events that fail a filter or lie outside the trial.
+template <bool HASH, int G>
+__device__ __forceinline__ void filter_group(const IdGroupT<G> &g, uint32_t valid, const uint32_t *sfilt,
+                                             const FusedFilter &f, int32_t zero_slot, int32_t (&idx)[G][4]) {
+    const uint32_t *shash = sfilt + f.n_fwords;
+#pragma unroll
+    for (int c = 0; c < G; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint32_t blk = (uint32_t)g.id[c][v] >> f.fshift;
+            uint32_t hit = ((valid >> (4 * c + v)) & 1u) & __builtin_amdgcn_ubfe(sfilt[blk >> 5], blk, 1u);
+            if (HASH) {
+                const uint32_t h = hash_slot((uint32_t)g.id[c][v], f.hshift);
+                hit &= __builtin_amdgcn_ubfe(shash[h >> 5], h, 1u);
+            }
+            idx[c][v] = hit ? g.id[c][v] : zero_slot;
+        }
+}
+
+// Adds the records of a group's events to the per-layer running sums,
+// chunk by chunk and in each chunk the lane's four events in order: for
+// every layer the order of the single-layer pass (FP32C: zeros skipped as
+// there; adding them would change no bit either).
+template <typename T, int NL, int G>
+__device__ __forceinline__ void add_dense_group(const int32_t (&idx)[G][4], const DenseRec<T, NL> *__restrict__ rec,
+                                                Acc<T> (&acc)[NL]) {
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+        DenseRec<T, NL> r[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) r[v] = rec[idx[c][v]];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                if (sizeof(T) == 8) {
+                    acc[l].add(r[v].v[l]);
+                } else if (r[v].v[l] != T(0)) {
+                    acc[l].add(r[v].v[l]);
+                }
+            }
+    }
+}
+
+// One wave per trial, the loads, filters and lane order of
+// k_trial_pass_fused; every event adds its record to NL running sums, so
+// each layer's YLT is bitwise the one of its own fused pass.  Lane l < n
+// writes layer l's year loss.
+template <typename T, int NL, bool FIXED, bool ALIGNED, bool HASH, int G>
+__global__ __launch_bounds__(1024) void k_trial_pass_dense(YetView y, const int64_t *__restrict__ off, FusedFilter f,
+                                                           int32_t zero_slot,
+                                                           const DenseRec<T, NL> *__restrict__ rec,
+                                                           double *const *__restrict__ ylts,
+                                                           const double *__restrict__ agg_ret,
+                                                           const double *__restrict__ agg_lim, int32_t n_layers) {
+    extern __shared__ uint32_t sfilt[];
+    load_filters(f, sfilt);
+    const int lane = lane_id();
+    double *my_ylt = nullptr;
+    double my_ret = 0.0, my_lim = 0.0;
+    if (lane < n_layers) {
+        my_ylt = ylts[lane];
+        my_ret = agg_ret[lane];
+        my_lim = agg_lim[lane];
+    }
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    constexpr int64_t kSpan = (int64_t)G * kChunkEvents;
+    const int64_t last_granule = (y.n_events - 1) & ~3LL;  // launched only with n_events >= 1
+    int64_t trial = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    TrialRange r{0, 0};
+    IdGroupT<G> cur;
+    uint32_t cur_valid = 0;
+    if (trial < y.n_trials) {
+        r = fused_range<FIXED>(y, off, trial);
+        cur_valid = load_group<FIXED, ALIGNED, G>(y, r, chunk_start(y, r.b), lane, last_granule, cur);
+    }
+    while (trial < y.n_trials) {
+        int32_t idx[G][4];
+        filter_group<HASH, G>(cur, cur_valid, sfilt, f, zero_slot, idx);
+        const int64_t next = trial + n_waves;
+        const TrialRange rn = fused_range<FIXED>(y, off, next < y.n_trials ? next : trial);
+        IdGroupT<G> nxt;
+        const uint32_t nxt_valid = load_group<FIXED, ALIGNED, G>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
+        Acc<T> acc[NL];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) acc[l] = Acc<T>::zero();
+        add_dense_group<T, NL, G>(idx, rec, acc);
+        constexpr int TG = FIXED ? G : 1;
+        for (int64_t base = chunk_start(y, r.b) + kSpan; base < r.e; base += (int64_t)TG * kChunkEvents) {
+            IdGroupT<TG> more;
+            const uint32_t mv = load_group<FIXED, ALIGNED, TG>(y, r, base, lane, last_granule, more);
+            int32_t mi[TG][4];
+            filter_group<HASH, TG>(more, mv, sfilt, f, zero_slot, mi);
+            add_dense_group<T, NL, TG>(mi, rec, acc);
+        }
+        double mine = 0.0;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const double S = wave_allreduce(acc[l]).value();
+            mine = lane == l ? S : mine;
+        }
+        if (lane < n_layers) my_ylt[trial] = clamp_excess(mine, my_ret, my_lim);
+        trial = next;
+        r = rn;
+        cur = nxt;
+        cur_valid = nxt_valid;
+    }
+}
+
+// --------------------------------------------------------------------------------------------
 // layers built on the device from a resident ELT pool: the fused table is
 // accumulated ELT by ELT in layer order (one kernel per ELT, an ELT holding
 // each event at most once), which is the order of the per-event sum of the
@@ -1473,6 +1637,80 @@ hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_fill_zero<double>), dim3(cu_count() * 4), dim3(256), 0, s, p, n);
     return hipGetLastError();
+}
+
+namespace {
+template <typename T, int NL>
+hipError_t dense_fill_t(const void *const *occ, int32_t n, const DenseTables &d, hipStream_t s) {
+    OccPtrs o{};
+    for (int l = 0; l < n; ++l) o.p[l] = occ[l];
+    uint32_t *filt = const_cast<uint32_t *>(d.filt);
+    hipLaunchKernelGGL((k_fill_zero<uint32_t>), dim3(64), dim3(256), 0, s, filt, (int64_t)(d.n_fwords + d.n_hwords));
+    const int64_t waves = ((int64_t)d.catalog + 1 + kWave - 1) / kWave;
+    int64_t blocks = (waves + 3) / 4;
+    const int64_t cap = (int64_t)cu_count() * 8;
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL((k_dense_fill<T, NL>), dim3((unsigned)blocks), dim3(256), 0, s, o, n, d.catalog,
+                       static_cast<DenseRec<T, NL> *>(const_cast<void *>(d.rec)), filt, d.fshift, filt + d.n_fwords,
+                       d.n_hwords, d.hshift);
+    return hipGetLastError();
+}
+
+template <typename T, int NL>
+hipError_t dense_pass_nl(const YetView &y, const DenseTables &d, hipStream_t s) {
+    const FusedFilter f{d.filt, d.n_fwords, d.fshift, d.n_hwords, d.hshift};
+    const size_t lds = (size_t)(f.n_fwords + f.n_hwords) * sizeof(uint32_t);
+    if (lds > (size_t)kFusedLdsBytes) return hipErrorInvalidValue;
+    const bool fixed = y.offsets == nullptr && y.aligned16 && y.events_per_trial > 0 && (y.events_per_trial % 4) == 0;
+    const bool hash = f.n_hwords > 0;
+    using K = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const DenseRec<T, NL> *, double *const *,
+                       const double *, const double *, int32_t);
+    // wider records hold more registers per chunk: groups of two chunks
+    // (the grouping changes when IDs are loaded, not the order of the adds)
+    constexpr int G = NL >= 4 ? 2 : 4;
+    const K ks[6] = {&k_trial_pass_dense<T, NL, true, true, false, G>, &k_trial_pass_dense<T, NL, false, true, false, G>,
+                     &k_trial_pass_dense<T, NL, false, false, false, G>, &k_trial_pass_dense<T, NL, true, true, true, G>,
+                     &k_trial_pass_dense<T, NL, false, true, true, G>, &k_trial_pass_dense<T, NL, false, false, true, G>};
+    const K k = ks[(fixed ? 0 : (y.aligned16 ? 1 : 2)) + (hash ? 3 : 0)];
+    hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(k), (int)kFusedLdsBytes);
+    if (e != hipSuccess) return e;
+    const int per_cu = lds > (size_t)kFusedLdsBytes / 2 ? 1 : 2;
+    const int grid = grid_for_trials(y.n_trials, 16, per_cu);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(1024), lds, s, y, y.offsets, f, d.catalog,
+                       static_cast<const DenseRec<T, NL> *>(d.rec), d.ylts, d.agg_ret, d.agg_lim, d.n_layers);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dense_pass_t(const YetView &y, const DenseTables &d, hipStream_t s) {
+    if (y.n_trials == 0) return hipSuccess;
+    switch (d.nl) {
+        case 1: return dense_pass_nl<T, 1>(y, d, s);
+        case 2: return dense_pass_nl<T, 2>(y, d, s);
+        case 4: return dense_pass_nl<T, 4>(y, d, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t dense_fill_w(const void *const *occ, int32_t n, const DenseTables &d, hipStream_t s) {
+    switch (d.nl) {
+        case 1: return dense_fill_t<T, 1>(occ, n, d, s);
+        case 2: return dense_fill_t<T, 2>(occ, n, d, s);
+        case 4: return dense_fill_t<T, 4>(occ, n, d, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+hipError_t launch_dense_fill(const void *const *occ, int32_t n_layers, bool fp64, const DenseTables &d, hipStream_t s) {
+    if (n_layers < 1 || n_layers > d.nl) return hipErrorInvalidValue;
+    return fp64 ? dense_fill_w<double>(occ, n_layers, d, s) : dense_fill_w<float>(occ, n_layers, d, s);
+}
+
+hipError_t launch_dense_pass(const YetView &y, const DenseTables &d, bool fp64, hipStream_t s) {
+    if (y.n_events == 0) return hipErrorInvalidValue;  // the caller writes zeros instead
+    return fp64 ? dense_pass_t<double>(y, d, s) : dense_pass_t<float>(y, d, s);
 }
 
 size_t batch_lds_bytes(int32_t n_layers, int threads) {

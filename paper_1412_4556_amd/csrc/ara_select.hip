@@ -494,7 +494,9 @@ hipError_t pml_tvar_noalloc(const double *const *d_ylts, int32_t n_ylt, int64_t 
     // the array's address on this device, looked up once per device with the
     // device current
     static std::atomic<char *> addr[kMaxDevices];
+    static std::atomic<bool> dirty[kMaxDevices];
     static std::mutex mu;
+    const SelLayout &lay = kNoAllocLayout;
     char *base = addr[dev].load(std::memory_order_acquire);
     if (!base) {
         std::lock_guard<std::mutex> g(mu);
@@ -505,19 +507,29 @@ hipError_t pml_tvar_noalloc(const double *const *d_ylts, int32_t n_ylt, int64_t 
             if (e != hipSuccess) return e;
             if (!p) return hipErrorInvalidSymbol;
             base = static_cast<char *>(p);
+            dirty[dev].store(true);
             addr[dev].store(base, std::memory_order_release);
         }
     }
-    // the call's flags and histograms start at zero whatever an earlier call
-    // left behind (a kernel, not a memset node, so the call can be captured)
-    const SelLayout &lay = kNoAllocLayout;
-    const int n_sel = n_ylt * n_rp;
-    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(kThreads), 0, s, reinterpret_cast<unsigned *>(base),
-                       (long long)kMaxYlt);
-    hipLaunchKernelGGL(k_zero_words, dim3(64), dim3(kThreads), 0, s, reinterpret_cast<unsigned *>(base + lay.hist),
-                       (long long)kPasses * n_sel * 256);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    return launch_select(base, lay, d_ylts, n_ylt, n, h_k, n_rp, nullptr, nullptr, d_pml, d_tvar, s);
+    // Every call that runs to its end leaves the flags and every histogram
+    // row it used at zero (each row is cleared two launches after its last
+    // reader).  The first call on a device, and a call after one that failed
+    // between its launches, clears them first with a kernel (not a memset
+    // node, so that the call can be captured).
+    if (dirty[dev].exchange(false)) {
+        hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(kThreads), 0, s, reinterpret_cast<unsigned *>(base),
+                           (long long)(lay.state / sizeof(unsigned)));
+        hipLaunchKernelGGL(k_zero_words, dim3(256), dim3(kThreads), 0, s,
+                           reinterpret_cast<unsigned *>(base + lay.hist),
+                           (long long)((lay.psum - lay.hist) / sizeof(unsigned)));
+        if ((e = hipGetLastError()) != hipSuccess) {
+            dirty[dev].store(true);
+            return e;
+        }
+    }
+    e = launch_select(base, lay, d_ylts, n_ylt, n, h_k, n_rp, nullptr, nullptr, d_pml, d_tvar, s);
+    if (e != hipSuccess) dirty[dev].store(true);
+    return e;
 }
 
 }  // namespace ara

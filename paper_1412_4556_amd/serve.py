@@ -11,12 +11,15 @@ Two servers with the same clock and the same device work per query:
 * ``serve_batched`` -- continuous batching.  Arrivals are admitted while the
   pool has a free layer slot (the pool's fixed table memory is the admission
   budget; a query that does not fit waits in the queue), and their fused
-  tables are built on the GPU on a build stream while the previous batch runs
+  tables are built on the GPU on a build stream while the previous group runs
   on the run stream.  Whenever the run stream can take more work, everything
-  admitted and built so far (up to ARA_MAX_BATCH layers) leaves as one
-  batched pass; two batch objects alternate so the records of the next batch
-  are built while the current one runs.  PML/TVaR of a whole batch come from
-  one call.
+  admitted and built so far (up to ARA_MAX_BATCH layers) leaves as one group:
+  one batched pass (dense records for up to 16 layers, sparse records above),
+  or a single-layer pass for a group of one, followed on the same stream by
+  PML/TVaR of the whole group into device memory (the entry point that
+  allocates nothing) and a copy of the results into pinned host memory.  The
+  host loop never waits for the device: it keeps admitting and building
+  arrivals and answers a group when its event has fired.
 * ``serve_one_at_a_time`` -- the baseline: each query in arrival order is
   built, run with the single-layer pass and reduced to PML/TVaR before the
   next one starts.
@@ -84,13 +87,11 @@ def _wait_until(clock, t):
 
 
 class BatchingServer:
-    """Continuous-batching server over one YET and one ELT pool.  Its streams
-    and its two batch objects live as long as the server, so repeated runs
-    pay no set-up; a group of fewer than ``min_batch`` queries runs as
-    back-to-back single-layer passes followed by one PML/TVaR call for the
-    group, all on the run stream, and is answered at once (the record pass
-    costs about the same for any number of layers, so below the crossover
-    ``warm_up`` measures it loses to separate passes)."""
+    """Continuous-batching server over one YET and one ELT pool.  Its streams,
+    batch objects and result buffers live as long as the server, so repeated
+    runs pay no set-up.  A group of fewer than ``min_batch`` queries runs as
+    back-to-back single-layer passes (below the crossover that ``warm_up``
+    measures, a batched pass loses to separate ones)."""
 
     def __init__(self, yet: A.Yet, pool: A.Pool, return_periods=(100.0, 250.0), max_batch: int = L.ARA_MAX_BATCH,
                  min_batch: int = 2):
@@ -100,26 +101,34 @@ class BatchingServer:
         self.min_batch = int(min_batch)
         self.run_s = torch.cuda.Stream()
         self.build_s = torch.cuda.Stream()
-        self.answer_s = torch.cuda.Stream()
-        self.batches = [None, None]
+        # two groups in flight at most; each holds a slot: a batch object and
+        # the device and pinned host buffers of its PML/TVaR
+        self.n_slots = 2
+        n_rp = len(self.return_periods)
+        self.batches = [None] * self.n_slots
+        self.dev_risk = [torch.empty(2 * self.max_batch * n_rp, dtype=torch.float64, device="cuda")
+                         for _ in range(self.n_slots)]
+        self.host_risk = [torch.empty(2 * self.max_batch * n_rp, dtype=torch.float64, pin_memory=True)
+                          for _ in range(self.n_slots)]
 
     def close(self):
         for b in self.batches:
             if b is not None:
                 b.close()
-        self.batches = [None, None]
+        self.batches = [None] * self.n_slots
 
     def serve(self, queries: Sequence[Query], keep_ylt: bool = False, progress=None) -> dict:
         """Serve the queries at their arrival times; ``progress(n_done)`` (if
         given) is called each time another 200 answers are out."""
         yet, pool = self.yet, self.pool
-        run_s, build_s, answer_s = self.run_s, self.build_s, self.answer_s
+        run_s, build_s = self.run_s, self.build_s
+        rps = self.return_periods
         T = yet.n_trials
         pending = collections.deque(sorted(queries, key=lambda q: q.arrival))
         waiting: collections.deque = collections.deque()   # arrived, not admitted
         built: List[Query] = []                           # admitted, table being built / ready
-        inflight: collections.deque = collections.deque()  # (queries, outs, event, batch slot)
-        free_batch = [0, 1]
+        inflight: collections.deque = collections.deque()  # (queries, outs, event, slot)
+        free_slots = list(range(self.n_slots))
         n_done = 0
         n_launches = 0
         t0 = time.perf_counter()
@@ -145,38 +154,30 @@ class BatchingServer:
                 q.admitted = clock()
                 built.append(q)
             # launch when the run stream has at most one group queued behind the running one
-            if built and len(inflight) < 2 and free_batch:
+            if built and free_slots:
                 group = built[:self.max_batch]
                 del built[:self.max_batch]
+                slot = free_slots.pop()
+                n = len(group)
                 with torch.cuda.stream(run_s):
                     outs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in group]
-                    if len(group) < max(2, self.min_batch):
-                        # below the crossover: the group's passes and one
-                        # PML/TVaR call for all of them on the run stream,
-                        # answered at once (as one query at a time would be,
-                        # with the risk metrics of the group in one call)
-                        for q, o in zip(group, outs):
-                            A.run_layer(yet, q.layer, out=o, stream=run_s)
-                        pml, tvar = A.pml_tvar_many(outs, self.return_periods, stream=run_s)
-                        t = clock()
-                        for i, q in enumerate(group):
-                            q.done = t
-                            q.batch_size = len(group)
-                            q.pml, q.tvar = pml[i], tvar[i]
-                            q.ylt = outs[i] if keep_ylt else None
-                            q.layer.close()
-                            q.layer = None
-                        n_done += len(group)
-                        n_launches += 1
-                        continue
+                if n < max(2, self.min_batch):
+                    for q, o in zip(group, outs):
+                        A.run_layer(yet, q.layer, out=o, stream=run_s)
+                else:
+                    layers = [q.layer for q in group]
+                    if self.batches[slot] is None:
+                        self.batches[slot] = A.Batch(yet, layers)
                     else:
-                        slot = free_batch.pop()
-                        layers = [q.layer for q in group]
-                        if self.batches[slot] is None:
-                            self.batches[slot] = A.Batch(yet, layers)
-                        else:
-                            self.batches[slot].rebuild(layers)
-                        self.batches[slot].run(outs, stream=run_s)
+                        self.batches[slot].rebuild(layers)
+                    self.batches[slot].run(outs, stream=run_s)
+                # PML of the group, then its TVaR, in one piece of device
+                # memory: one copy brings both to the host
+                m = n * len(rps)
+                dev, host = self.dev_risk[slot], self.host_risk[slot]
+                A.pml_tvar_many_noalloc(outs, rps, dev[:m], dev[m:2 * m], stream=run_s)
+                with torch.cuda.stream(run_s):
+                    host[:2 * m].copy_(dev[:2 * m], non_blocking=True)
                     ev = torch.cuda.Event()
                     ev.record(run_s)
                 inflight.append((group, outs, ev, slot))
@@ -184,18 +185,17 @@ class BatchingServer:
             # completion, in launch order
             if inflight and inflight[0][2].query():
                 group, outs, ev, slot = inflight.popleft()
-                answer_s.wait_event(ev)
-                pml, tvar = A.pml_tvar_many(outs, self.return_periods, stream=answer_s)
                 t = clock()
+                n, r = len(group), len(rps)
+                res = self.host_risk[slot][:2 * n * r].numpy().reshape(2, n, r).copy()
                 for i, q in enumerate(group):
                     q.done = t
                     q.batch_size = len(group)
-                    q.pml, q.tvar = pml[i], tvar[i]
+                    q.pml, q.tvar = res[0, i], res[1, i]
                     q.ylt = outs[i] if keep_ylt else None
                     q.layer.close()
                     q.layer = None
-                if slot is not None:
-                    free_batch.append(slot)
+                free_slots.append(slot)
                 n_done += len(group)
                 continue
             if not inflight and not built and not waiting and pending:

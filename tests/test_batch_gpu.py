@@ -37,7 +37,13 @@ def _yet(ids, off, T, C, K=0, misalign=False):
 
 CASES = [
     # name, trials, mean_len, catalog, n_layers, max_elts, elt_size, fixed_len, misalign
+    # (up to 16 layers: dense records in passes of up to 4 layers; above: sparse records)
     ("poisson_12", 3000, 200.0, 20000, 12, 8, 3000, False, False),
+    ("poisson_16", 2000, 250.0, 20000, 16, 6, 2000, False, False),
+    ("poisson_17", 2000, 250.0, 20000, 17, 6, 2000, False, False),
+    ("poisson_3", 2500, 300.0, 40000, 3, 8, 5000, False, False),
+    ("fixed_2", 900, 512, 30000, 2, 5, 5000, True, False),
+    ("one_layer", 1500, 100.0, 10000, 1, 4, 2000, False, False),
     ("poisson_64", 2000, 300.0, 50000, 64, 6, 4000, False, False),
     ("fixed_1000", 600, 1000, 30000, 9, 5, 5000, True, False),
     ("fixed_7_misaligned", 700, 7, 3000, 5, 4, 600, True, True),
@@ -155,14 +161,15 @@ def _shared_layers(n, C, seed):
     return out
 
 
+@pytest.mark.parametrize("n", [12, 20])
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
-def test_batch_rebuild_same_size_larger_overflow(prec):
+def test_batch_rebuild_same_size_larger_overflow(prec, n):
     """Regression: a batch that replayed a captured graph and is then rebuilt
     with the same number of layers but more overflow entries (its overflow
     area is reallocated) must not replay the old graph's pointers; a run on a
     second stream right after one on the first, and a rebuild right after a
     run, are ordered after the earlier run by the library."""
-    T, C, n = 2500, 3000, 12
+    T, C = 2500, 3000
     ids, off, _ = W.random_case(4242, T, 150.0, C, 1, 1)
     yet = _yet(ids, off, T, C)
     few = [A.Layer(yet, s, prec, "fused") for s in _disjoint_layers(n, C, 200, 1)]
@@ -180,7 +187,8 @@ def test_batch_rebuild_same_size_larger_overflow(prec):
     # no synchronisation between the run above and this rebuild
     outs_a = b.run()
     b.rebuild(many)
-    assert b.device_bytes > small_bytes  # the overflow area was reallocated
+    if n > 16:
+        assert b.device_bytes > small_bytes  # the overflow area was reallocated
     s2 = torch.cuda.Stream()
     outs_b = b.run(stream=s2)
     outs_c = b.run()  # default stream right after a run on s2
@@ -198,4 +206,29 @@ def test_batch_rebuild_same_size_larger_overflow(prec):
     torch.cuda.synchronize()
     for l in range(n):
         assert np.array_equal(outs_d[l].cpu().numpy(), single_few[l]), ("rebuilt back", l)
+    b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_batch_rebuild_across_forms(prec):
+    """One batch object rebuilt between the dense form (up to 16 layers, in
+    passes of up to 4) and the sparse one, and between dense widths, without
+    synchronising in between: every run bitwise its layers' own passes."""
+    T, C = 1800, 8000
+    ids, off, _ = W.random_case(99, T, 120.0, C, 1, 1, empty_frac=0.05)
+    yet = _yet(ids, off, T, C)
+    specs = _layers(5, 40, C, 6, 1500)
+    layers = [A.Layer(yet, sp, prec, "fused") for sp in specs]
+    singles = [A.run_layer(yet, l).cpu().numpy() for l in layers]
+    b = A.Batch(yet, layers[:2])
+    pending = []
+    for lo, hi in ((0, 2), (3, 40), (1, 4), (5, 21), (7, 23), (2, 18), (0, 1), (9, 13), (0, 40)):
+        if b.n_layers != hi - lo or lo != 0:
+            b.rebuild(layers[lo:hi])
+        outs = b.run()
+        pending.append((lo, hi, outs))
+    torch.cuda.synchronize()
+    for lo, hi, outs in pending:
+        for k, o in enumerate(outs):
+            assert np.array_equal(o.cpu().numpy(), singles[lo + k]), (lo, hi, k)
     b.close()

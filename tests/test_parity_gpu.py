@@ -143,7 +143,8 @@ EDGE = [
      False),
     ("hashed_filter_3M_misaligned", dict(seed=45, n_trials=1200, mean_len=350.0, catalog=3_000_000, n_elts=8,
                                          elt_size=60_000), True),
-    # mean trial length above 768: the YLT pass reads 1,280-event groups
+    # trials longer than a 1,024-event group: the YLT pass reads the group,
+    # then the rest of the trial one 256-event chunk at a time
     ("wide_groups_hashed", dict(seed=47, n_trials=900, mean_len=1000.0, catalog=2_000_000, n_elts=8,
                                 elt_size=30_000), False),
 ]

@@ -84,7 +84,7 @@ def test_noalloc_nan_and_limits():
     # beyond the static scratch: rejected on the host, nothing launched
     many = _ylts(4, 5, 1_000)
     with pytest.raises(L.AraError) as ei:
-        _noalloc(many, [2.0] * 13)  # 65 selections
+        _noalloc(many * 3, [2.0] * 9)  # 135 selections
     assert ei.value.name == "ARA_ERR_UNSUPPORTED"
     with pytest.raises(L.AraError) as ei:
         _noalloc(many[:1], [2000.0])  # k = floor(1000 / 2000) = 0
