@@ -1086,7 +1086,13 @@ hipError_t tune_batch(ara_batch b, hipStream_t s) {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) {
-            b->cfg = it->second;
+            // the shape was tuned for another layer count of the bucket: the
+            // per-wave accumulators grow with the count, so narrow the
+            // work-group until they fit the LDS
+            ara::BatchLaunch c = it->second;
+            while (c.threads > ara::kWave && ara::batch_lds_bytes(b->n, c.threads) > 160u * 1024u)
+                c.threads -= ara::kWave;
+            b->cfg = c;
             b->tuned = true;
             return hipSuccess;
         }
@@ -1095,7 +1101,10 @@ hipError_t tune_batch(ara_batch b, hipStream_t s) {
     std::vector<ara::BatchLaunch> cands;
     if (force) {
         int t = 256, w = 1;
-        if (std::sscanf(force, "%d,%d", &t, &w) == 2 && t >= 64 && t <= 512 && t % 64 == 0 && w >= 1) cands.push_back({t, w});
+        if (std::sscanf(force, "%d,%d", &t, &w) == 2 && t >= 64 && t <= 512 && t % 64 == 0 && w >= 1) {
+            while (t > ara::kWave && ara::batch_lds_bytes(b->n, t) > 160u * 1024u) t -= ara::kWave;
+            cands.push_back({t, w});
+        }
     }
     if (cands.empty())
         for (int t : {256, 512})

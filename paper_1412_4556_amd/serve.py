@@ -110,12 +110,14 @@ class BatchingServer:
                          for _ in range(self.n_slots)]
         self.host_risk = [torch.empty(2 * self.max_batch * n_rp, dtype=torch.float64, pin_memory=True)
                           for _ in range(self.n_slots)]
+        self.ylt_bufs = [[] for _ in range(self.n_slots)]
 
     def close(self):
         for b in self.batches:
             if b is not None:
                 b.close()
         self.batches = [None] * self.n_slots
+        self.ylt_bufs = [[] for _ in range(self.n_slots)]
 
     def serve(self, queries: Sequence[Query], keep_ylt: bool = False, progress=None) -> dict:
         """Serve the queries at their arrival times; ``progress(n_done)`` (if
@@ -145,7 +147,9 @@ class BatchingServer:
             while waiting:
                 q = waiting[0]
                 try:
-                    q.layer = _build(pool, q, build_s)
+                    # with nothing on the run stream, build there (the pass
+                    # then needs no wait on another stream's event)
+                    q.layer = _build(pool, q, run_s if not inflight else build_s)
                 except L.AraError as e:
                     if e.name == "ARA_ERR_OOM":
                         break
@@ -159,8 +163,16 @@ class BatchingServer:
                 del built[:self.max_batch]
                 slot = free_slots.pop()
                 n = len(group)
-                with torch.cuda.stream(run_s):
-                    outs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in group]
+                if keep_ylt:
+                    with torch.cuda.stream(run_s):
+                        outs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in group]
+                else:
+                    # the slot's own YLT buffers (a slot is reused only after
+                    # its group has been answered)
+                    bufs = self.ylt_bufs[slot]
+                    while len(bufs) < n:
+                        bufs.append(torch.empty(T, dtype=torch.float64, device="cuda"))
+                    outs = bufs[:n]
                 if n < max(2, self.min_batch):
                     for q, o in zip(group, outs):
                         A.run_layer(yet, q.layer, out=o, stream=run_s)

@@ -232,3 +232,30 @@ def test_batch_rebuild_across_forms(prec):
         for k, o in enumerate(outs):
             assert np.array_equal(o.cpu().numpy(), singles[lo + k]), (lo, hi, k)
     b.close()
+
+
+def test_batch_tuned_shape_fits_every_layer_count(monkeypatch):
+    """A launch shape tuned for one layer count is reused for the other
+    counts of its power-of-two bucket; its work-group is narrowed when the
+    per-wave accumulators of a larger count would not fit the LDS (512
+    threads fit 33 FP64 layers, not 64)."""
+    T, C = 1234, 6000
+    ids, off, _ = W.random_case(1234, T, 80.0, C, 1, 1)
+    yet = _yet(ids, off, T, C)
+    layers = [A.Layer(yet, sp, "fp64", "fused") for sp in _layers(8, 64, C, 3, 800)]
+    singles = [A.run_layer(yet, l).cpu().numpy() for l in layers]
+    monkeypatch.setenv("ARA_BATCH_LAUNCH", "512,1")
+    b = A.Batch(yet, layers[:33])
+    outs = b.run()
+    assert b.launch_config == (512, 1)
+    monkeypatch.delenv("ARA_BATCH_LAUNCH")
+    b.rebuild(layers)
+    outs64 = b.run()
+    threads, _ = b.launch_config
+    assert threads <= 256
+    torch.cuda.synchronize()
+    for l in range(33):
+        assert np.array_equal(outs[l].cpu().numpy(), singles[l])
+    for l in range(64):
+        assert np.array_equal(outs64[l].cpu().numpy(), singles[l])
+    b.close()
