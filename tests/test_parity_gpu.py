@@ -493,3 +493,44 @@ def test_fused_build_at_paper_catalogue(prec):
     # and a valid build still works after the failed ones
     again = A.Layer(yet, spec, prec, "fused")
     assert np.array_equal(A.run_layer(yet, again).cpu().numpy(), yf)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_fused_build_concentrated_elts(prec):
+    """ELTs whose events crowd into one 8,192-event range of the catalogue
+    (the part one work-group of the one-launch build owns): the table is
+    still bitwise the compact layout's, and a duplicate ID or a bad loss
+    inside the crowded range is still found."""
+    C = 200_000
+    rng = np.random.default_rng(2027)
+    eids, elos = [], []
+    for j in range(8):
+        eids.append(rng.choice(8192, size=6000, replace=False).astype(np.int32))  # all in the first range
+        elos.append(rng.lognormal(8.0, 2.0, 6000))
+    for j in range(2):
+        eids.append(rng.choice(C, size=20_000, replace=False).astype(np.int32))
+        elos.append(rng.lognormal(8.0, 2.0, 20_000))
+    J = len(eids)
+    ret = np.array([np.quantile(l, 0.1) for l in elos])
+    lim = np.array([np.quantile(l, 0.9) for l in elos])
+    spec = W.LayerSpec(eids, elos, ret, lim, 500.0, 1e6, 1e4, 1e8)
+    T = 2000
+    ids = np.concatenate([rng.integers(0, 8192, size=T * 200 // 2), rng.integers(0, C, size=T * 200 // 2)]).astype(np.int32)
+    rng.shuffle(ids)
+    yet = A.Yet(torch.from_numpy(ids).cuda(), None, T, C, 200)
+    yf = A.run_layer(yet, A.Layer(yet, spec, prec, "fused")).cpu().numpy()
+    yc = A.run_layer(yet, A.Layer(yet, spec, prec, "compact")).cpu().numpy()
+    assert np.array_equal(yf, yc)
+    assert (yf > 0).mean() > 0.05
+    ref = oracle_run(ids, None, T, C, 200, spec)
+    assert_close_to_oracle(yf, ref, prec)
+    bad_ids = [a.copy() for a in eids]
+    bad_ids[3][5999] = bad_ids[3][17]
+    with pytest.raises(L.AraError) as ei:
+        A.Layer(yet, W.LayerSpec(bad_ids, elos, ret, lim, 500.0, 1e6, 1e4, 1e8), prec, "fused")
+    assert ei.value.name == "ARA_ERR_DUP_EVENT"
+    bad_los = [a.copy() for a in elos]
+    bad_los[5][100] = float("nan")
+    with pytest.raises(L.AraError) as ei:
+        A.Layer(yet, W.LayerSpec(eids, bad_los, ret, lim, 500.0, 1e6, 1e4, 1e8), prec, "fused")
+    assert ei.value.name == "ARA_ERR_VALUE"
