@@ -201,7 +201,7 @@ def precision_runs(A, W, torch):
 
 
 def cpu_baseline(wl, spec, target_s, gpu_ylt=None, gpu_pml_tvar=None, rps=(), gpu_ylt32=None,
-                 gpu_pml_tvar32=None, precision=None):
+                 gpu_pml_tvar32=None, precision=None, single_full=False):
     """The oracle on a bounded sample of the same workload, on the host cores;
     with the GPU's YLT of the timed pass, also the GPU's error on the sample
     (|y - y_oracle| / G per trial, G the trial's gross looked-up loss) and,
@@ -238,6 +238,11 @@ def cpu_baseline(wl, spec, target_s, gpu_ylt=None, gpu_pml_tvar=None, rps=(), gp
     res["single_thread"] = {"value": ev1 * J / dt1, "unit": "lookups/s", "cores": 1,
                             "sample": f"first {n1} trials ({ev1} trial-events x {J} ELTs), {dt1:.1f} s "
                                       f"incl. direct-table build"}
+    if single_full:
+        # the whole workload on one core (the paper's sequential form; minutes)
+        dtf, evf, _ = run(wl.yet.n_trials, 1)
+        res["single_thread_full"] = {"value": evf * J / dtf, "unit": "lookups/s", "cores": 1, "seconds": dtf,
+                                     "sample": f"all {wl.yet.n_trials} trials ({evf} trial-events x {J} ELTs)"}
     # and whole on the two small workloads (parity: 10k x 1000 events, 4 ELTs;
     # precision: 10k Poisson(1000) trials, 4 ELTs of Pareto losses)
     small = {}
@@ -312,6 +317,21 @@ def batch_leg(A, W, torch, n_trials, steps, precision="fp64"):
     batch_ms = timed(lambda: batch.run(outs), steps)
     seq_ms = timed(lambda: [A.run_layer(yet, l, out=o) for l, o in zip(layers, seq)], max(1, steps // 2))
     same = all(torch.equal(a, b) for a, b in zip(outs, seq))
+    # small batches (dense records, one pass per group of 4 layers) of the
+    # first n layers against their single-layer passes
+    single = [timed(lambda l=l, o=o: A.run_layer(yet, l, out=o), 3) for l, o in zip(layers[:16], seq[:16])]
+    small = []
+    for n in (2, 4, 8, 16):
+        sb = A.Batch(yet, layers[:n])
+        so = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in range(n)]
+        sb.run(so)
+        ms = timed(lambda: sb.run(so), 3)
+        small.append({"n_layers": n, "batched_ms": ms, "single_passes_ms": sum(single[:n]),
+                      "speedup": sum(single[:n]) / ms, "launch_group_chunks": sb.launch_group,
+                      "bitwise_equal_to_single": all(torch.equal(a, b) for a, b in zip(so, seq[:n]))})
+        log(f"batch leg: {n} layers batched {ms:.2f} ms vs {sum(single[:n]):.2f} ms as single passes")
+        sb.close()
+        del so
     J = [s.n_elts for s in wl.layers]
     lt = len(layers) * T
     log(f"batch leg: batched {batch_ms:.2f} ms vs sequential {seq_ms:.2f} ms ({seq_ms / batch_ms:.1f}x), "
@@ -322,9 +342,11 @@ def batch_leg(A, W, torch, n_trials, steps, precision="fp64"):
            "batched_layer_trials_per_s": lt / (batch_ms * 1e-3),
            "sequential_layer_trials_per_s": lt / (seq_ms * 1e-3),
            "batched_lookups_per_s": float(sum(J)) * n_events / (batch_ms * 1e-3),
-           "launch_config": list(batch.launch_config), "record_bytes": batch.device_bytes,
+           "launch_config": list(batch.launch_config), "launch_group_chunks": batch.launch_group,
+           "record_bytes": batch.device_bytes,
            "batch_build_ms": batch_build_ms, "first_run_ms_incl_tuning": first_run_ms,
-           "layer_build_s_total": layer_build_s, "bitwise_equal_to_sequential": bool(same)}
+           "layer_build_s_total": layer_build_s, "bitwise_equal_to_sequential": bool(same),
+           "small_batches": small}
     # programs of 8 layers each, then the portfolio of the 8 programs, and
     # their PML/TVaR (100 and 250 years)
     progs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in range(8)]
@@ -413,6 +435,8 @@ def main():
     ap.add_argument("--trials", type=int, default=1_000_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-single-thread-full", action="store_true",
+                    help="also time the oracle on one core over the whole workload (minutes)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-trials", type=int, default=1_000_000)
@@ -576,7 +600,7 @@ def main():
         y64, y32 = (ylt_host, ylt2_host) if args.precision == "fp64" else (ylt2_host, ylt_host)
         p64, p32 = ((pml, tvar), pt2) if args.precision == "fp64" else (pt2, (pml, tvar))
         cpu = cpu_baseline(wl, spec, args.cpu_seconds, gpu_ylt=y64, gpu_pml_tvar=p64, rps=rps, gpu_ylt32=y32,
-                           gpu_pml_tvar32=p32, precision=precision)
+                           gpu_pml_tvar32=p32, precision=precision, single_full=args.cpu_single_thread_full)
         log(f"cpu baseline {cpu['value']:.3e} lookups/s on {cpu['cores']} threads")
 
     rec = {

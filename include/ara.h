@@ -193,9 +193,11 @@ ara_status ara_run_layer_max_occurrence(ara_yet yet, ara_layer layer, double *d_
  * ara_create_batch is synchronous; the batch owns its device memory.
  * ara_run_batch writes d_ylts[l] (binary64 [n_trials], caller-owned) for
  * every layer l of the batch; each is bitwise the YLT ara_run_layer gives
- * for that layer.  The launch shape is chosen on the first run by timing
- * candidates (and remembered per precision, power-of-two layer count and
- * YET), then the pass is replayed from a HIP graph captured once.
+ * for that layer.  The launch shape (work-group size, work-groups per CU
+ * and the number of 256-event chunks loaded per step) is chosen on the first
+ * run by timing candidates (and remembered per precision, power-of-two layer
+ * count or record width, and YET), then the pass is replayed from a HIP
+ * graph captured once.
  * Asynchronous on hip_stream. */
 typedef struct ara_batch_s *ara_batch;
 ara_status ara_create_batch(ara_yet yet, const ara_layer *layers, int32_t n_layers, ara_batch *out);
@@ -216,6 +218,11 @@ size_t ara_batch_device_bytes(ara_batch batch);
 ara_status ara_batch_rebuild(ara_batch batch, const ara_layer *layers, int32_t n_layers);
 /* Launch shape chosen for the batch (0, 0 before its first run). */
 ara_status ara_batch_launch_config(ara_batch batch, int32_t *threads, int32_t *wg_per_cu);
+/* Number of 256-event chunks of a trial the batch's pass loads per step
+ * (2, 4 or 8; for a dense batch, that of its first group of 4 layers),
+ * chosen with the launch shape by timing candidates on the first run (0
+ * before it). */
+ara_status ara_batch_launch_group(ara_batch batch, int32_t *group);
 void ara_destroy_batch(ara_batch batch);
 
 /* One-shot form: ara_create_batch + ara_run_batch + ara_destroy_batch

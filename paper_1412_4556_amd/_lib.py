@@ -43,6 +43,7 @@ SIGNATURES = {
     "ara_run_batch": (_I32, [_P, _P, _P]),
     "ara_batch_device_bytes": (_SZ, [_P]),
     "ara_batch_launch_config": (_I32, [_P, _P, _P]),
+    "ara_batch_launch_group": (_I32, [_P, _P]),
     "ara_destroy_batch": (None, [_P]),
     "ara_batch_rebuild": (_I32, [_P, _P, _I32]),
     "ara_create_pool": (_I32, [_P, _I32, _P, _P, _P, _I32, _I32, _P]),

@@ -234,6 +234,13 @@ class Batch:
         L.check(L.lib().ara_batch_launch_config(self._h, ctypes.byref(t), ctypes.byref(w)))
         return int(t.value), int(w.value)
 
+    @property
+    def launch_group(self) -> int:
+        """256-event chunks per load step chosen for the pass (0 before the first run)."""
+        g = ctypes.c_int32()
+        L.check(L.lib().ara_batch_launch_group(self._h, ctypes.byref(g)))
+        return int(g.value)
+
     def rebuild(self, layers: Sequence[Layer]):
         n = len(layers)
         hs = (ctypes.c_void_p * n)(*[l.handle.value for l in layers])

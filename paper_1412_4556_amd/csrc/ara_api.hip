@@ -81,7 +81,9 @@ struct ara_batch_s {
     double **d_ylts = nullptr;  // device array of the YLT pointers of the last run
     double *d_agg = nullptr;    // [2 * ARA_MAX_BATCH]: aggregate retentions, then limits
     std::vector<double *> h_ylts;
-    ara::BatchLaunch cfg{256, 1};
+    ara::BatchLaunch cfg{256, 1, 4};
+    // dense form: tuned chunk-group size per record width (1, 2, 4: index 0..2)
+    int dgroup[3] = {0, 0, 0};
     bool tuned = false;
     bool use_graph = true;
     hipGraph_t graph = nullptr;
@@ -92,7 +94,7 @@ struct ara_batch_s {
     ara::BatchTables graph_tables{};
     const void *graph_drec = nullptr;
     const uint32_t *graph_dfilt = nullptr;
-    ara::BatchLaunch graph_cfg{0, 0};
+    ara::BatchLaunch graph_cfg{0, 0, 0};
     // recorded on the caller's stream after every run: a rebuild, and a run
     // on another stream, wait for it before they overwrite what the last
     // run reads (records, overflow entries, terms, YLT pointers)
@@ -1007,6 +1009,7 @@ ara_status ara_batch_rebuild(ara_batch b, const ara_layer *layers, int32_t n_lay
         // on instead of capturing a graph per size
         drop_graph(b);
         b->tuned = false;
+        b->dgroup[0] = b->dgroup[1] = b->dgroup[2] = 0;
         b->use_graph = b->n == 0;
         b->n = n_layers;
         b->dense = dense;
@@ -1097,20 +1100,23 @@ hipError_t tune_batch(ara_batch b, hipStream_t s) {
             return hipSuccess;
         }
     }
-    const char *force = std::getenv("ARA_BATCH_LAUNCH");  // "threads,wg_per_cu" skips the search
+    // "threads,wg_per_cu[,group]" skips the search
+    const char *force = std::getenv("ARA_BATCH_LAUNCH");
     std::vector<ara::BatchLaunch> cands;
     if (force) {
-        int t = 256, w = 1;
-        if (std::sscanf(force, "%d,%d", &t, &w) == 2 && t >= 64 && t <= 512 && t % 64 == 0 && w >= 1) {
+        int t = 256, w = 1, g = 4;
+        const int got = std::sscanf(force, "%d,%d,%d", &t, &w, &g);
+        if (got >= 2 && t >= 64 && t <= 512 && t % 64 == 0 && w >= 1 && (g == 2 || g == 4 || g == 8)) {
             while (t > ara::kWave && ara::batch_lds_bytes(b->n, t) > 160u * 1024u) t -= ara::kWave;
-            cands.push_back({t, w});
+            cands.push_back({t, w, g});
         }
     }
     if (cands.empty())
-        for (int t : {256, 512})
-            for (int w : {1, 2, 4})
-                if (ara::batch_lds_bytes(b->n, t) * (size_t)w <= 160u * 1024u) cands.push_back({t, w});
-    if (cands.empty()) cands.push_back({64, 1});
+        for (int g : {2, 4, 8})
+            for (int t : {256, 512})
+                for (int w : {1, 2, 4})
+                    if (ara::batch_lds_bytes(b->n, t) * (size_t)w <= 160u * 1024u) cands.push_back({t, w, g});
+    if (cands.empty()) cands.push_back({64, 1, 4});
     const ara::BatchTables tb = batch_tables(b);
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
@@ -1145,16 +1151,77 @@ hipError_t tune_batch(ara_batch b, hipStream_t s) {
     return hipSuccess;
 }
 
+int nl_index(int nl) { return nl == 1 ? 0 : (nl == 2 ? 1 : 2); }
+
 // One launch of the batch's pass in its current form.
 hipError_t pass_once(ara_batch b, hipStream_t s) {
     const bool fp64 = b->precision == ARA_FP64;
     if (b->dense) {
         hipError_t e = hipSuccess;
-        for (int sub = 0; sub < dense_subs(b->n) && e == hipSuccess; ++sub)
-            e = ara::launch_dense_pass(b->yv, dense_tables(b, sub), fp64, s);
+        for (int sub = 0; sub < dense_subs(b->n) && e == hipSuccess; ++sub) {
+            const ara::DenseTables t = dense_tables(b, sub);
+            e = ara::launch_dense_pass(b->yv, t, fp64, b->dgroup[nl_index(t.nl)], s);
+        }
         return e;
     }
     return ara::launch_batch_pass(b->yv, batch_tables(b), fp64, b->cfg, s);
+}
+
+// Chunk-group size of the dense pass per record width, chosen by timing the
+// candidates on the batch's first sub-table of that width, remembered per
+// (precision, width, trial count, YET form) for the process.
+std::map<std::tuple<int, int, int64_t, int, int>, int> g_dense_tuned;
+
+hipError_t tune_dense(ara_batch b, hipStream_t s) {
+    const bool fp64 = b->precision == ARA_FP64;
+    const int form = b->yv.offsets ? 1 : 0;
+    for (int sub = 0; sub < dense_subs(b->n); ++sub) {
+        const ara::DenseTables t = dense_tables(b, sub);
+        const int ix = nl_index(t.nl);
+        if (b->dgroup[ix]) continue;
+        const auto key = std::make_tuple(b->precision, t.nl, b->yv.n_trials, form, (int)b->yv.aligned16);
+        {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            auto it = g_dense_tuned.find(key);
+            if (it != g_dense_tuned.end()) {
+                b->dgroup[ix] = it->second;
+                continue;
+            }
+        }
+        std::vector<int> cands = t.nl >= 4 ? std::vector<int>{2} : std::vector<int>{2, 4};
+        int best = cands[0];
+        if (cands.size() > 1) {
+            hipEvent_t e0, e1;
+            hipError_t e = hipEventCreate(&e0);
+            if (e == hipSuccess) e = hipEventCreate(&e1);
+            float best_ms = 1e30f;
+            for (int g : cands) {
+                if (e != hipSuccess) break;
+                e = ara::launch_dense_pass(b->yv, t, fp64, g, s);  // warm-up
+                float tot = 0.0f;
+                for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+                    e = hipEventRecord(e0, s);
+                    if (e == hipSuccess) e = ara::launch_dense_pass(b->yv, t, fp64, g, s);
+                    if (e == hipSuccess) e = hipEventRecord(e1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0.0f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    tot += ms;
+                }
+                if (e == hipSuccess && tot < best_ms) {
+                    best_ms = tot;
+                    best = g;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            if (e != hipSuccess) return e;
+        }
+        b->dgroup[ix] = best;
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_dense_tuned[key] = best;
+    }
+    return hipSuccess;
 }
 
 hipError_t capture_batch(ara_batch b) {
@@ -1196,7 +1263,7 @@ bool graph_current(const ara_batch b) {
     return now.rec == was.rec && now.ovf_lid == was.ovf_lid && now.ovf_val == was.ovf_val &&
            now.ylts == was.ylts && now.agg_ret == was.agg_ret && now.agg_lim == was.agg_lim &&
            now.n_layers == was.n_layers && b->cfg.threads == b->graph_cfg.threads &&
-           b->cfg.wg_per_cu == b->graph_cfg.wg_per_cu;
+           b->cfg.wg_per_cu == b->graph_cfg.wg_per_cu && b->cfg.group == b->graph_cfg.group;
 }
 
 // Launch the pass (graph replay or direct launch) and record the batch's
@@ -1247,9 +1314,10 @@ ara_status ara_run_batch(ara_batch batch, double *const *d_ylts, void *hip_strea
             e = ara::launch_fill_zero(d_ylts[l], batch->yv.n_trials, s);
         if (e != hipSuccess) return hip_fail(e, "zero YLTs");
     } else {
-        if (!batch->tuned && !batch->dense) {
-            e = tune_batch(batch, s);
+        if (!batch->tuned) {
+            e = batch->dense ? tune_dense(batch, s) : tune_batch(batch, s);
             if (e != hipSuccess) return hip_fail(e, "batch launch tuning");
+            batch->tuned = true;
         }
         ara_status st = launch_batch(batch, s);
         if (st != ARA_OK) return st;
@@ -1264,13 +1332,25 @@ ara_status ara_run_batch(ara_batch batch, double *const *d_ylts, void *hip_strea
 ara_status ara_batch_launch_config(ara_batch batch, int32_t *threads, int32_t *wg_per_cu) {
     if (!batch || !threads || !wg_per_cu) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
     if (batch->dense) {
-        // fixed shape: 1024-thread groups, the LDS filters allow one per CU
-        *threads = batch->ran ? 1024 : 0;
-        *wg_per_cu = batch->ran ? 1 : 0;
+        // 1024-thread groups, the LDS filters allow one per CU
+        *threads = batch->tuned ? 1024 : 0;
+        *wg_per_cu = batch->tuned ? 1 : 0;
         return ARA_OK;
     }
     *threads = batch->tuned ? batch->cfg.threads : 0;
     *wg_per_cu = batch->tuned ? batch->cfg.wg_per_cu : 0;
+    return ARA_OK;
+}
+
+ara_status ara_batch_launch_group(ara_batch batch, int32_t *group) {
+    if (!batch || !group) return fail(ARA_ERR_INVALID_ARG, "NULL argument");
+    if (!batch->tuned) {
+        *group = 0;
+    } else if (batch->dense) {
+        *group = batch->dgroup[nl_index(dense_tables(batch, 0).nl)];
+    } else {
+        *group = batch->cfg.group;
+    }
     return ARA_OK;
 }
 

@@ -167,6 +167,7 @@ struct DenseTables {
 struct BatchLaunch {
     int threads;     // work-group size (multiple of 64)
     int wg_per_cu;   // work-groups per CU requested (clamped by LDS)
+    int group;       // 256-event chunks of a trial loaded per step (2, 4 or 8)
 };
 
 // occ pointers of the layers -> records.  Returns the total number of
@@ -180,7 +181,8 @@ hipError_t launch_batch_pass(const YetView &y, const BatchTables &b, bool fp64, 
 // Dense form: records and filters from the layers' fused tables (filter
 // words cleared first), then the pass.
 hipError_t launch_dense_fill(const void *const *occ, int32_t n_layers, bool fp64, const DenseTables &d, hipStream_t s);
-hipError_t launch_dense_pass(const YetView &y, const DenseTables &d, bool fp64, hipStream_t s);
+// group: 256-event chunks loaded per step, 2 or 4 (2 only for 4-wide records)
+hipError_t launch_dense_pass(const YetView &y, const DenseTables &d, bool fp64, int group, hipStream_t s);
 size_t batch_lds_bytes(int32_t n_layers, int threads);
 // Fused table of a layer, built on the GPU: the ELTs idx[0..n) of device
 // arrays d_ids / d_loss (ELT k at host offsets off[k] .. off[k + 1]) added

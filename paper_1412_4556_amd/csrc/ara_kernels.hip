@@ -878,7 +878,7 @@ __device__ __forceinline__ void wave_lds_fence() {
 // handled by lane i is added to acc[l][i]; at the end of the trial lane l
 // folds row l with the butterfly order of wave_allreduce, so layer l's YLT is
 // bitwise the one of its own pass.
-template <typename T, bool FIXED, bool ALIGNED>
+template <typename T, bool FIXED, bool ALIGNED, int G>
 __global__ __launch_bounds__(512) void k_trial_pass_batch(YetView y, const int64_t *__restrict__ off, BatchTables b) {
     extern __shared__ uint64_t lds_raw[];
     const int lane = lane_id();
@@ -894,38 +894,38 @@ __global__ __launch_bounds__(512) void k_trial_pass_batch(YetView y, const int64
     }
     for (int l = 0; l < n_layers; ++l) acc[l * kAccStride + lane] = Acc<T>::zero();
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    constexpr int64_t kSpan = (int64_t)kGroup * 4 * kWave;
+    constexpr int64_t kSpan = (int64_t)G * kChunkEvents;
     const int64_t last_granule = (y.n_events - 1) & ~3LL;  // launched only with n_events >= 1
     int64_t trial = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     TrialRange r{0, 0};
-    IdGroup cur;
+    IdGroupT<G> cur;
     uint32_t cur_valid = 0;
     if (trial < y.n_trials) {
         r = fused_range<FIXED>(y, off, trial);
-        cur_valid = load_group<FIXED, ALIGNED>(y, r, chunk_start(y, r.b), lane, last_granule, cur);
+        cur_valid = load_group<FIXED, ALIGNED, G>(y, r, chunk_start(y, r.b), lane, last_granule, cur);
     }
     while (trial < y.n_trials) {
         const int64_t next = trial + n_waves;
         const TrialRange rn = fused_range<FIXED>(y, off, next < y.n_trials ? next : trial);
-        IdGroup nxt;
-        const uint32_t nxt_valid = load_group<FIXED, ALIGNED>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
+        IdGroupT<G> nxt;
+        const uint32_t nxt_valid = load_group<FIXED, ALIGNED, G>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
         // records double-buffered across chunks: the loads of chunk c + 1 are
         // in flight while chunk c is added to the accumulators
         int64_t base = chunk_start(y, r.b);
-        IdGroup g = cur;
+        IdGroupT<G> g = cur;
         uint32_t valid = cur_valid;
         Record<T> rr[2][4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) rr[0][v] = rec[g.id[0][v]];
         while (true) {
 #pragma unroll
-            for (int c = 0; c < kGroup; ++c) {
+            for (int c = 0; c < G; ++c) {
                 // chunks that start past the trial's end hold no event (a
                 // variable-length trial's last group is mostly such padding)
                 if (c > 0 && base + (int64_t)c * 4 * kWave >= r.e) break;
                 OvHeads<T> oh;
                 load_ov_heads(rr[c & 1], (valid >> (4 * c)) & 0xfu, b, oh);
-                if (c + 1 < kGroup) {
+                if (c + 1 < G) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) rr[(c + 1) & 1][v] = rec[g.id[c + 1][v]];
                 }
@@ -935,7 +935,7 @@ __global__ __launch_bounds__(512) void k_trial_pass_batch(YetView y, const int64
             }
             base += kSpan;
             if (base >= r.e) break;
-            valid = load_group<FIXED, ALIGNED>(y, r, base, lane, last_granule, g);
+            valid = load_group<FIXED, ALIGNED, G>(y, r, base, lane, last_granule, g);
 #pragma unroll
             for (int v = 0; v < 4; ++v) rr[0][v] = rec[g.id[0][v]];
         }
@@ -1520,12 +1520,20 @@ hipError_t batch_fill_t(const void *const *occ, int32_t n, int32_t catalog, cons
                        static_cast<Record<T> *>(rec), ovf_lid, static_cast<T *>(ovf_val), cursor);
     return hipGetLastError();
 }
+template <typename T, int G>
+auto batch_kernel(bool fixed, bool aligned) {
+    return fixed ? &k_trial_pass_batch<T, true, true, G>
+                 : (aligned ? &k_trial_pass_batch<T, false, true, G> : &k_trial_pass_batch<T, false, false, G>);
+}
+
 template <typename T>
 hipError_t batch_pass_t(const YetView &y, const BatchTables &b, const BatchLaunch &cfg, hipStream_t s) {
     if (y.n_trials == 0) return hipSuccess;
     const bool fixed = y.offsets == nullptr && y.aligned16 && y.events_per_trial > 0 && (y.events_per_trial % 4) == 0;
-    auto kern = fixed ? &k_trial_pass_batch<T, true, true>
-                      : (y.aligned16 ? &k_trial_pass_batch<T, false, true> : &k_trial_pass_batch<T, false, false>);
+    const bool al = y.aligned16 != 0;
+    if (cfg.group != 2 && cfg.group != 4 && cfg.group != 8) return hipErrorInvalidValue;
+    auto kern = cfg.group == 2 ? batch_kernel<T, 2>(fixed, al)
+                               : (cfg.group == 8 ? batch_kernel<T, 8>(fixed, al) : batch_kernel<T, 4>(fixed, al));
     const size_t lds = batch_lds_bytes(b.n_layers, cfg.threads);
     if (lds > 160u * 1024u || cfg.threads < kWave || cfg.threads > 512 || cfg.threads % kWave) return hipErrorInvalidValue;
     hipError_t ae = allow_dynamic_lds(reinterpret_cast<const void *>(kern), 160 * 1024);
@@ -1656,8 +1664,8 @@ hipError_t dense_fill_t(const void *const *occ, int32_t n, const DenseTables &d,
     return hipGetLastError();
 }
 
-template <typename T, int NL>
-hipError_t dense_pass_nl(const YetView &y, const DenseTables &d, hipStream_t s) {
+template <typename T, int NL, int G>
+hipError_t dense_pass_nlg(const YetView &y, const DenseTables &d, hipStream_t s) {
     const FusedFilter f{d.filt, d.n_fwords, d.fshift, d.n_hwords, d.hshift};
     const size_t lds = (size_t)(f.n_fwords + f.n_hwords) * sizeof(uint32_t);
     if (lds > (size_t)kFusedLdsBytes) return hipErrorInvalidValue;
@@ -1665,9 +1673,6 @@ hipError_t dense_pass_nl(const YetView &y, const DenseTables &d, hipStream_t s) 
     const bool hash = f.n_hwords > 0;
     using K = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const DenseRec<T, NL> *, double *const *,
                        const double *, const double *, int32_t);
-    // wider records hold more registers per chunk: groups of two chunks
-    // (the grouping changes when IDs are loaded, not the order of the adds)
-    constexpr int G = NL >= 4 ? 2 : 4;
     const K ks[6] = {&k_trial_pass_dense<T, NL, true, true, false, G>, &k_trial_pass_dense<T, NL, false, true, false, G>,
                      &k_trial_pass_dense<T, NL, false, false, false, G>, &k_trial_pass_dense<T, NL, true, true, true, G>,
                      &k_trial_pass_dense<T, NL, false, true, true, G>, &k_trial_pass_dense<T, NL, false, false, true, G>};
@@ -1681,13 +1686,17 @@ hipError_t dense_pass_nl(const YetView &y, const DenseTables &d, hipStream_t s) 
     return hipGetLastError();
 }
 
+// Groups of 2 or 4 chunks (the grouping changes when IDs are loaded, not
+// the order of the adds); 4-wide records hold more registers per chunk and
+// take groups of 2 only.
 template <typename T>
-hipError_t dense_pass_t(const YetView &y, const DenseTables &d, hipStream_t s) {
+hipError_t dense_pass_t(const YetView &y, const DenseTables &d, int group, hipStream_t s) {
     if (y.n_trials == 0) return hipSuccess;
+    if (group != 2 && group != 4) return hipErrorInvalidValue;
     switch (d.nl) {
-        case 1: return dense_pass_nl<T, 1>(y, d, s);
-        case 2: return dense_pass_nl<T, 2>(y, d, s);
-        case 4: return dense_pass_nl<T, 4>(y, d, s);
+        case 1: return group == 2 ? dense_pass_nlg<T, 1, 2>(y, d, s) : dense_pass_nlg<T, 1, 4>(y, d, s);
+        case 2: return group == 2 ? dense_pass_nlg<T, 2, 2>(y, d, s) : dense_pass_nlg<T, 2, 4>(y, d, s);
+        case 4: return dense_pass_nlg<T, 4, 2>(y, d, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1708,9 +1717,9 @@ hipError_t launch_dense_fill(const void *const *occ, int32_t n_layers, bool fp64
     return fp64 ? dense_fill_w<double>(occ, n_layers, d, s) : dense_fill_w<float>(occ, n_layers, d, s);
 }
 
-hipError_t launch_dense_pass(const YetView &y, const DenseTables &d, bool fp64, hipStream_t s) {
+hipError_t launch_dense_pass(const YetView &y, const DenseTables &d, bool fp64, int group, hipStream_t s) {
     if (y.n_events == 0) return hipErrorInvalidValue;  // the caller writes zeros instead
-    return fp64 ? dense_pass_t<double>(y, d, s) : dense_pass_t<float>(y, d, s);
+    return fp64 ? dense_pass_t<double>(y, d, group, s) : dense_pass_t<float>(y, d, group, s);
 }
 
 size_t batch_lds_bytes(int32_t n_layers, int threads) {

@@ -72,6 +72,7 @@ def test_batch_equals_single_layer_passes(case, prec):
     torch.cuda.synchronize()
     threads, per_cu = batch.launch_config
     assert threads % 64 == 0 and per_cu >= 1
+    assert batch.launch_group in ((2, 4) if n <= 16 else (2, 4, 8))
     for l in range(n):
         assert np.array_equal(outs[l].cpu().numpy(), singles[l]), (name, l)
     # a second run (graph replay) into new buffers gives the same bits
@@ -244,10 +245,10 @@ def test_batch_tuned_shape_fits_every_layer_count(monkeypatch):
     yet = _yet(ids, off, T, C)
     layers = [A.Layer(yet, sp, "fp64", "fused") for sp in _layers(8, 64, C, 3, 800)]
     singles = [A.run_layer(yet, l).cpu().numpy() for l in layers]
-    monkeypatch.setenv("ARA_BATCH_LAUNCH", "512,1")
+    monkeypatch.setenv("ARA_BATCH_LAUNCH", "512,1,8")
     b = A.Batch(yet, layers[:33])
     outs = b.run()
-    assert b.launch_config == (512, 1)
+    assert b.launch_config == (512, 1) and b.launch_group == 8
     monkeypatch.delenv("ARA_BATCH_LAUNCH")
     b.rebuild(layers)
     outs64 = b.run()
