@@ -180,10 +180,11 @@ ara_status ara_run_layer_max_occurrence(ara_yet yet, ara_layer layer, double *d_
  * and per catalogue event, one dense record of the event's occurrence losses
  * in those layers, and LDS filters of the events with any non-zero loss:
  * one pass over the YET per group of 4 layers, gathering a record only for
- * events that pass the filters.  A larger batch holds one 64-byte (FP64) or
- * 32-byte (FP32C) record per catalogue event of the layers in which its
- * occurrence loss is non-zero and those losses, and reads one record per
- * trial-event in a single pass.  Either way the pass keeps one running sum
+ * events that pass the filters.  A larger batch, or a small one whose
+ * groups' non-zero events cover too much of the catalogue for that to pay,
+ * holds one 64-byte (FP64) or 32-byte (FP32C) record per catalogue event of
+ * the layers in which its occurrence loss is non-zero and those losses, and
+ * reads one record per trial-event in a single pass.  Either way the pass keeps one running sum
  * per (layer, lane), adding each layer's losses in the same order as the
  * single-layer pass.
  *   layers    1 .. ARA_MAX_BATCH layer handles, all built against this YET

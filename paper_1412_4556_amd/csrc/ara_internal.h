@@ -179,8 +179,10 @@ hipError_t launch_batch_fill(const void *const *occ, int32_t n_layers, int32_t c
                              unsigned long long *d_ovf_cursor, hipStream_t s);
 hipError_t launch_batch_pass(const YetView &y, const BatchTables &b, bool fp64, const BatchLaunch &cfg, hipStream_t s);
 // Dense form: records and filters from the layers' fused tables (filter
-// words cleared first), then the pass.
-hipError_t launch_dense_fill(const void *const *occ, int32_t n_layers, bool fp64, const DenseTables &d, hipStream_t s);
+// words cleared first; *d_union_count, cleared by the caller, receives the
+// number of events with any non-zero value), then the pass.
+hipError_t launch_dense_fill(const void *const *occ, int32_t n_layers, bool fp64, const DenseTables &d,
+                             unsigned long long *d_union_count, hipStream_t s);
 // group: 256-event chunks loaded per step, 2 or 4 (2 only for 4-wide records)
 hipError_t launch_dense_pass(const YetView &y, const DenseTables &d, bool fp64, int group, hipStream_t s);
 size_t batch_lds_bytes(int32_t n_layers, int threads);

@@ -976,11 +976,12 @@ struct alignas(sizeof(T) * NL <= 16 ? sizeof(T) * NL : 16) DenseRec {
 // one word, or two when blocks are single events) and set with one atomic
 // OR per word; the hashed filter gets one atomic OR per non-zero event.
 // Filter words are cleared beforehand.
+// *union_count receives the number of events with any non-zero value.
 template <typename T, int NL>
 __global__ __launch_bounds__(256) void k_dense_fill(OccPtrs occ, int32_t n_layers, int32_t catalog,
                                                     DenseRec<T, NL> *__restrict__ rec, uint32_t *__restrict__ filt,
                                                     int32_t fshift, uint32_t *__restrict__ hwords, int32_t n_hwords,
-                                                    int32_t hshift) {
+                                                    int32_t hshift, unsigned long long *union_count) {
     const int lane = lane_id();
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -1007,6 +1008,8 @@ __global__ __launch_bounds__(256) void k_dense_fill(OccPtrs occ, int32_t n_layer
         }
         if (lane == 0 && lo) atomicOr(&filt[w_first], lo);
         if (lane == 0 && hi) atomicOr(&filt[w_first + 1], hi);
+        const unsigned long long members = __ballot(any != 0u);
+        if (lane == 0 && members) atomicAdd(union_count, (unsigned long long)__popcll(members));
         if (n_hwords > 0 && any) {
             const uint32_t h = hash_slot((uint32_t)e, hshift);
             atomicOr(&hwords[h >> 5], 1u << (h & 31u));
@@ -1649,7 +1652,8 @@ hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t s) {
 
 namespace {
 template <typename T, int NL>
-hipError_t dense_fill_t(const void *const *occ, int32_t n, const DenseTables &d, hipStream_t s) {
+hipError_t dense_fill_t(const void *const *occ, int32_t n, const DenseTables &d, unsigned long long *ucount,
+                        hipStream_t s) {
     OccPtrs o{};
     for (int l = 0; l < n; ++l) o.p[l] = occ[l];
     uint32_t *filt = const_cast<uint32_t *>(d.filt);
@@ -1660,7 +1664,7 @@ hipError_t dense_fill_t(const void *const *occ, int32_t n, const DenseTables &d,
     if (blocks > cap) blocks = cap;
     hipLaunchKernelGGL((k_dense_fill<T, NL>), dim3((unsigned)blocks), dim3(256), 0, s, o, n, d.catalog,
                        static_cast<DenseRec<T, NL> *>(const_cast<void *>(d.rec)), filt, d.fshift, filt + d.n_fwords,
-                       d.n_hwords, d.hshift);
+                       d.n_hwords, d.hshift, ucount);
     return hipGetLastError();
 }
 
@@ -1702,19 +1706,22 @@ hipError_t dense_pass_t(const YetView &y, const DenseTables &d, int group, hipSt
 }
 
 template <typename T>
-hipError_t dense_fill_w(const void *const *occ, int32_t n, const DenseTables &d, hipStream_t s) {
+hipError_t dense_fill_w(const void *const *occ, int32_t n, const DenseTables &d, unsigned long long *ucount,
+                        hipStream_t s) {
     switch (d.nl) {
-        case 1: return dense_fill_t<T, 1>(occ, n, d, s);
-        case 2: return dense_fill_t<T, 2>(occ, n, d, s);
-        case 4: return dense_fill_t<T, 4>(occ, n, d, s);
+        case 1: return dense_fill_t<T, 1>(occ, n, d, ucount, s);
+        case 2: return dense_fill_t<T, 2>(occ, n, d, ucount, s);
+        case 4: return dense_fill_t<T, 4>(occ, n, d, ucount, s);
         default: return hipErrorInvalidValue;
     }
 }
 }  // namespace
 
-hipError_t launch_dense_fill(const void *const *occ, int32_t n_layers, bool fp64, const DenseTables &d, hipStream_t s) {
+hipError_t launch_dense_fill(const void *const *occ, int32_t n_layers, bool fp64, const DenseTables &d,
+                             unsigned long long *d_union_count, hipStream_t s) {
     if (n_layers < 1 || n_layers > d.nl) return hipErrorInvalidValue;
-    return fp64 ? dense_fill_w<double>(occ, n_layers, d, s) : dense_fill_w<float>(occ, n_layers, d, s);
+    return fp64 ? dense_fill_w<double>(occ, n_layers, d, d_union_count, s)
+                : dense_fill_w<float>(occ, n_layers, d, d_union_count, s);
 }
 
 hipError_t launch_dense_pass(const YetView &y, const DenseTables &d, bool fp64, int group, hipStream_t s) {
