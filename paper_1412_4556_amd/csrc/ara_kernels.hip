@@ -1506,12 +1506,18 @@ hipError_t launch_trial_pass_events(const YetView &y, const LayerHost &L, double
 }
 
 namespace {
+// One thread per catalogue event (256-thread blocks).
+int event_blocks(int32_t catalog) {
+    const int64_t b = ((int64_t)catalog + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > (1LL << 20) ? (1LL << 20) : b));
+}
+
 template <typename T>
 hipError_t batch_count_t(const void *const *occ, int32_t n, int32_t catalog, int32_t *cnt, unsigned long long *tot,
                          hipStream_t s) {
     OccPtrs o{};
     for (int l = 0; l < n; ++l) o.p[l] = occ[l];
-    hipLaunchKernelGGL((k_batch_count<T>), dim3(cu_count() * 4), dim3(256), 0, s, o, n, catalog, cnt, tot);
+    hipLaunchKernelGGL((k_batch_count<T>), dim3(event_blocks(catalog)), dim3(256), 0, s, o, n, catalog, cnt, tot);
     return hipGetLastError();
 }
 template <typename T>
@@ -1519,7 +1525,7 @@ hipError_t batch_fill_t(const void *const *occ, int32_t n, int32_t catalog, cons
                         uint8_t *ovf_lid, void *ovf_val, unsigned long long *cursor, hipStream_t s) {
     OccPtrs o{};
     for (int l = 0; l < n; ++l) o.p[l] = occ[l];
-    hipLaunchKernelGGL((k_batch_fill<T>), dim3(cu_count() * 4), dim3(256), 0, s, o, n, catalog, cnt,
+    hipLaunchKernelGGL((k_batch_fill<T>), dim3(event_blocks(catalog)), dim3(256), 0, s, o, n, catalog, cnt,
                        static_cast<Record<T> *>(rec), ovf_lid, static_cast<T *>(ovf_val), cursor);
     return hipGetLastError();
 }
@@ -1658,10 +1664,10 @@ hipError_t dense_fill_t(const void *const *occ, int32_t n, const DenseTables &d,
     for (int l = 0; l < n; ++l) o.p[l] = occ[l];
     uint32_t *filt = const_cast<uint32_t *>(d.filt);
     hipLaunchKernelGGL((k_fill_zero<uint32_t>), dim3(64), dim3(256), 0, s, filt, (int64_t)(d.n_fwords + d.n_hwords));
+    // one wave per 64 events: every load of the fill in flight at once
     const int64_t waves = ((int64_t)d.catalog + 1 + kWave - 1) / kWave;
     int64_t blocks = (waves + 3) / 4;
-    const int64_t cap = (int64_t)cu_count() * 8;
-    if (blocks > cap) blocks = cap;
+    if (blocks > (1LL << 20)) blocks = 1LL << 20;
     hipLaunchKernelGGL((k_dense_fill<T, NL>), dim3((unsigned)blocks), dim3(256), 0, s, o, n, d.catalog,
                        static_cast<DenseRec<T, NL> *>(const_cast<void *>(d.rec)), filt, d.fshift, filt + d.n_fwords,
                        d.n_hwords, d.hshift, ucount);
