@@ -220,9 +220,13 @@ ara_status ara_batch_rebuild(ara_batch batch, const ara_layer *layers, int32_t n
 /* Launch shape chosen for the batch (0, 0 before its first run). */
 ara_status ara_batch_launch_config(ara_batch batch, int32_t *threads, int32_t *wg_per_cu);
 /* Number of 256-event chunks of a trial the batch's pass loads per step
- * (2, 4 or 8; for a dense batch, that of its first group of 4 layers),
+ * (2, 4 or 8; for a dense batch, that of its first group of 4 layers), or
+ * 1 for the pipelined record pass (one chunk per step, each chunk's ID,
+ * record and overflow loads issued over the three steps before its sums),
  * chosen with the launch shape by timing candidates on the first run (0
- * before it). */
+ * before it).  The environment variable ARA_BATCH_LAUNCH =
+ * "threads,wg_per_cu,group" forces a shape for the sparse record pass
+ * (not remembered for later batches). */
 ara_status ara_batch_launch_group(ara_batch batch, int32_t *group);
 void ara_destroy_batch(ara_batch batch);
 

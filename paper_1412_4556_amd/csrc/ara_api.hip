@@ -971,9 +971,10 @@ ara_status rebuild_sparse(ara_batch b, const void *const *occ, int32_t n_layers,
     if (e == hipSuccess) e = hipMemcpyAsync(h_ctr, b->d_ctr, sizeof(h_ctr), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "counting the batch records");
-    // at least one overflow slot: the pass prefetches overflow entries of
-    // every event at clamped indices, slot 0 for events without any
-    const unsigned long long n_ovf = h_ctr[0] > 0 ? h_ctr[0] : 1;
+    // at least one block of four overflow slots: the passes prefetch
+    // overflow entries of every event at clamped indices, block 0 for
+    // events without any
+    const unsigned long long n_ovf = h_ctr[0] > 4 ? h_ctr[0] : 4;
     if (n_ovf >= (1ULL << 32)) return fail(ARA_ERR_UNSUPPORTED, "too many overflow entries for one batch");
     if (n_ovf > b->ovf_cap) {
         // grows only; the stream is idle here, the last run finished
@@ -1115,7 +1116,9 @@ hipError_t tune_batch(ara_batch b, hipStream_t s) {
     int n_bucket = 1;  // layer counts share a tuned shape per power of two
     while (n_bucket < b->n) n_bucket <<= 1;
     const auto key = std::make_tuple(b->precision, n_bucket, b->yv.n_trials, form, (int)b->yv.aligned16);
-    {
+    // "threads,wg_per_cu[,group]" skips the search (and is not remembered)
+    const char *force = std::getenv("ARA_BATCH_LAUNCH");
+    if (!force) {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) {
@@ -1130,22 +1133,23 @@ hipError_t tune_batch(ara_batch b, hipStream_t s) {
             return hipSuccess;
         }
     }
-    // "threads,wg_per_cu[,group]" skips the search
-    const char *force = std::getenv("ARA_BATCH_LAUNCH");
     std::vector<ara::BatchLaunch> cands;
     if (force) {
         int t = 256, w = 1, g = 4;
         const int got = std::sscanf(force, "%d,%d,%d", &t, &w, &g);
-        if (got >= 2 && t >= 64 && t <= 512 && t % 64 == 0 && w >= 1 && (g == 2 || g == 4 || g == 8)) {
+        if (got >= 2 && t >= 64 && t <= (g == 1 ? ara::kMaxStreamThreads : 512) && t % 64 == 0 && w >= 1 &&
+            (g == 1 || g == 2 || g == 4 || g == 8)) {
             while (t > ara::kWave && ara::batch_lds_bytes(b->n, t) > 160u * 1024u) t -= ara::kWave;
             cands.push_back({t, w, g});
         }
     }
     if (cands.empty())
-        for (int g : {2, 4, 8})
+        for (int g : {1, 2, 4, 8})
             for (int t : {256, 512})
                 for (int w : {1, 2, 4})
-                    if (ara::batch_lds_bytes(b->n, t) * (size_t)w <= 160u * 1024u) cands.push_back({t, w, g});
+                    if ((g != 1 || t <= ara::kMaxStreamThreads) &&
+                        ara::batch_lds_bytes(b->n, t) * (size_t)w <= 160u * 1024u)
+                        cands.push_back({t, w, g});
     if (cands.empty()) cands.push_back({64, 1, 4});
     const ara::BatchTables tb = batch_tables(b);
     hipEvent_t e0, e1;
@@ -1176,8 +1180,10 @@ hipError_t tune_batch(ara_batch b, hipStream_t s) {
     if (e != hipSuccess) return e;
     b->cfg = best_cfg;
     b->tuned = true;
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tuned[key] = best_cfg;
+    if (cands.size() > 1) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tuned[key] = best_cfg;
+    }
     return hipSuccess;
 }
 

@@ -117,7 +117,8 @@ hipError_t launch_trial_pass_events(const YetView &y, const LayerHost &L, double
 // values.  An event with more entries than fit keeps kRecVals - 1 inline,
 // marks byte 7 with kOverflowMark, holds the number of further entries in
 // byte kRecVals - 1 and their start in the overflow arrays in value slot
-// kRecVals - 1 (as a uint32).
+// kRecVals - 1 (as a uint32).  Each event's overflow entries start on a
+// multiple of four and fill whole blocks of four (padding: kNoLayer, 0).
 constexpr uint8_t kNoLayer = 0xff, kOverflowMark = 0xfe;
 template <typename T>
 struct RecFormat;
@@ -167,8 +168,12 @@ struct DenseTables {
 struct BatchLaunch {
     int threads;     // work-group size (multiple of 64)
     int wg_per_cu;   // work-groups per CU requested (clamped by LDS)
-    int group;       // 256-event chunks of a trial loaded per step (2, 4 or 8)
+    int group;       // 256-event chunks of a trial loaded per step (2, 4 or 8),
+                     // or 1: the pipelined pass (one chunk per step, loads
+                     // staged over three steps)
 };
+// Largest work-group of the pipelined batched pass.
+constexpr int kMaxStreamThreads = 256;
 
 // occ pointers of the layers -> records.  Returns the total number of
 // overflow entries through *d_ovf_total (device) in the counting phase.

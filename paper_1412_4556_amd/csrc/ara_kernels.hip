@@ -739,6 +739,11 @@ struct OccPtrs {
     const void *p[ARA_MAX_BATCH];
 };
 
+// An event's overflow entries start on a multiple of four in the overflow
+// arrays and take whole blocks of four (the pipelined pass reads a block's
+// four layer indices as one 32-bit word and its values as 16-byte loads).
+__device__ __forceinline__ int ovf_span(int n) { return (n + 3) & ~3; }
+
 template <typename T>
 __global__ void k_batch_count(OccPtrs occ, int32_t n_layers, int32_t catalog, int32_t *__restrict__ count,
                               unsigned long long *ovf_total) {
@@ -747,7 +752,7 @@ __global__ void k_batch_count(OccPtrs occ, int32_t n_layers, int32_t catalog, in
         int n = 0;
         for (int l = 0; l < n_layers; ++l) n += static_cast<const T *>(occ.p[l])[e] != T(0);
         count[e] = n;
-        if (n > KV) atomicAdd(ovf_total, (unsigned long long)(n - (KV - 1)));
+        if (n > KV) atomicAdd(ovf_total, (unsigned long long)ovf_span(n - (KV - 1)));
     }
 }
 
@@ -766,7 +771,7 @@ __global__ void k_batch_fill(OccPtrs occ, int32_t n_layers, int32_t catalog, con
         const bool ovf = n > KV;
         const int n_in = ovf ? KV - 1 : KV;
         unsigned long long pos = 0;
-        if (ovf) pos = atomicAdd(cursor, (unsigned long long)(n - n_in));
+        if (ovf) pos = atomicAdd(cursor, (unsigned long long)ovf_span(n - n_in));
         int k = 0;
         for (int l = 0; l < n_layers; ++l) {
             const T v = static_cast<const T *>(occ.p[l])[e];
@@ -781,6 +786,11 @@ __global__ void k_batch_fill(OccPtrs occ, int32_t n_layers, int32_t catalog, con
             ++k;
         }
         if (ovf) {
+            // the padding of the event's last block of four
+            for (int q = k - n_in; q < ovf_span(n - n_in); ++q) {
+                ovf_lid[pos + q] = kNoLayer;
+                ovf_val[pos + q] = T(0);
+            }
             r.lid[7] = kOverflowMark;
             r.lid[KV - 1] = (uint8_t)(n - n_in);
             const uint32_t p32 = (uint32_t)pos;
@@ -957,6 +967,281 @@ __global__ __launch_bounds__(512) void k_trial_pass_batch(YetView y, const int64
         r = rn;
         cur = nxt;
         cur_valid = nxt_valid;
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// pipelined batched pass: the same records, sums and lane order as
+// k_trial_pass_batch, with the loads of a wave's chunks staged so that no
+// step waits for a load issued in the same step.  A wave walks the chunks
+// of its trials as one sequence (an empty trial counts as one chunk without
+// events); at step k it
+//   1. requests the first overflow block of every event of chunk k + 1
+//      (whose records arrived),
+//   2. requests the records of chunk k + 2 (whose IDs arrived),
+//   3. requests the IDs of chunk k + 3,
+//   4. adds chunk k's entries to the per-lane accumulators and, after a
+//      trial's last chunk, writes its year losses.
+// Every load is consumed one step after it was issued, so the step's LDS
+// work hides its latency.  Three rotating slots hold a chunk each.
+
+// First block of four overflow entries of an event.
+template <typename T>
+struct OvBlock {
+    uint32_t lid4;  // layer index of entry j in bits 8j .. 8j + 7
+    T val[4];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_ov_block(const BatchTables &b, uint32_t pos, OvBlock<T> &o) {
+    o.lid4 = *reinterpret_cast<const uint32_t *>(b.ovf_lid + pos);
+    if (sizeof(T) == 8) {
+        const double2 *v = reinterpret_cast<const double2 *>(static_cast<const double *>(b.ovf_val) + pos);
+        const double2 a = v[0], c = v[1];
+        o.val[0] = (T)a.x; o.val[1] = (T)a.y; o.val[2] = (T)c.x; o.val[3] = (T)c.y;
+    } else {
+        const float4 a = *reinterpret_cast<const float4 *>(static_cast<const float *>(b.ovf_val) + pos);
+        o.val[0] = (T)a.x; o.val[1] = (T)a.y; o.val[2] = (T)a.z; o.val[3] = (T)a.w;
+    }
+}
+
+// Overflow start and count of an event's record (0, 0 without overflow).
+template <typename T>
+__device__ __forceinline__ void ov_of(const Record<T> &r, uint32_t &pos, int &cnt) {
+    constexpr int KV = RecFormat<T>::kVals;
+    const bool ovf = r.lid[7] == kOverflowMark;
+    uint32_t p;
+    __builtin_memcpy(&p, &r.val[KV - 1], sizeof(p));
+    pos = ovf ? p : 0u;
+    cnt = ovf ? (int)r.lid[KV - 1] : 0;
+}
+
+template <typename T>
+struct StreamSlot {
+    int32_t id[4];      // IDs of the chunk whose records are requested next
+    uint32_t nvalid;    // their in-trial mask
+    uint32_t valid;     // mask of the chunk whose records are in rr
+    Record<T> rr[4];
+    OvBlock<T> ob[4];
+    int64_t ntrial, trial;  // trial of the chunk of id / of rr (-1: no chunk)
+    int nlast, last;        // that chunk ends its trial
+};
+
+// A wave's walk over the chunks of its trials.
+struct ChunkCursor {
+    int64_t trial;  // trial of the next chunk (>= n_trials: done)
+    int64_t base;   // its first position
+    TrialRange r;
+};
+
+template <bool FIXED>
+__device__ __forceinline__ void cursor_enter(const YetView &y, const int64_t *__restrict__ off, ChunkCursor &cc) {
+    if (cc.trial < y.n_trials) {
+        cc.r = fused_range<FIXED>(y, off, cc.trial);
+        cc.base = chunk_start(y, cc.r.b);
+    }
+}
+
+// Step 3: the next chunk's IDs into s (raw: masked when its records are
+// requested), its mask and trial; advances the cursor.
+template <typename T, bool FIXED, bool ALIGNED>
+__device__ __forceinline__ void stream_next(const YetView &y, const int64_t *__restrict__ off, ChunkCursor &cc,
+                                            int64_t n_waves, int lane, int64_t last_granule, StreamSlot<T> &s) {
+    if (cc.trial >= y.n_trials) {
+        s.ntrial = -1;
+        s.nlast = 0;
+        s.nvalid = 0;
+        return;
+    }
+    const int64_t p = cc.base + 4 * lane;
+    if (ALIGNED) {
+        const int64_t lim = load_limit(FIXED, cc.r.b, cc.r.e, last_granule);
+        const int4 v = stream_ids4(y.ids + clamped_granule(p, lim));
+        s.id[0] = v.x; s.id[1] = v.y; s.id[2] = v.z; s.id[3] = v.w;
+        s.nvalid = granule_valid(FIXED, p, cc.r.b, cc.r.e);
+    } else {
+        // element loads at in-trial positions (else the trial's first, or
+        // the YET's first element for an empty trial), masked afterwards
+        const int64_t safe = cc.r.e > cc.r.b ? cc.r.b : 0;
+        uint32_t m = 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t q = p + v;
+            const bool in = q >= cc.r.b && q < cc.r.e;
+            s.id[v] = y.ids[in ? q : safe];
+            m |= (in ? 1u : 0u) << v;
+        }
+        s.nvalid = m;
+    }
+    s.ntrial = cc.trial;
+    cc.base += kChunkEvents;
+    s.nlast = cc.base >= cc.r.e ? 1 : 0;
+    if (s.nlast) {
+        cc.trial += n_waves;
+        cursor_enter<FIXED>(y, off, cc);
+    }
+}
+
+// Step 2: records of the slot's chunk (events outside the trial read the
+// record of event 0 and are never added).
+template <typename T>
+__device__ __forceinline__ void stream_records(const Record<T> *__restrict__ rec, StreamSlot<T> &s) {
+    s.valid = s.nvalid;
+    s.trial = s.ntrial;
+    s.last = s.nlast;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s.rr[v] = rec[((s.valid >> v) & 1u) ? s.id[v] : 0];
+}
+
+// Step 1: first overflow block of each event (block 0 for events without).
+template <typename T>
+__device__ __forceinline__ void stream_heads(const BatchTables &b, StreamSlot<T> &s) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        uint32_t pos;
+        int cnt;
+        ov_of(s.rr[v], pos, cnt);
+        load_ov_block(b, ((s.valid >> v) & 1u) ? pos : 0u, s.ob[v]);
+    }
+}
+
+// Adds a batch of entries with distinct layers: every accumulator is read
+// before any is written, so the reads are in flight together.
+template <typename T, int N>
+__device__ __forceinline__ void add_distinct(Acc<T> *acc, int lane, const bool (&act)[N], const uint32_t (&lid)[N],
+                                             const T (&val)[N]) {
+    Acc<T> a[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (act[k]) a[k] = acc[lid[k] * kAccStride + lane];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (act[k]) {
+            a[k].add(val[k]);
+            acc[lid[k] * kAccStride + lane] = a[k];
+        }
+}
+
+// Step 4: the chunk's events in lane order; an event's entries (inline,
+// first overflow block, further blocks) hold distinct layers.
+template <typename T>
+__device__ __forceinline__ void stream_add(const BatchTables &b, const StreamSlot<T> &s, Acc<T> *acc, int lane) {
+    constexpr int KV = RecFormat<T>::kVals;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const Record<T> &r = s.rr[v];
+        const bool in = ((s.valid >> v) & 1u) != 0u;
+        uint32_t pos;
+        int cnt;
+        ov_of(r, pos, cnt);
+        const int n_in = cnt > 0 ? KV - 1 : KV;
+        bool act[KV + 4];
+        uint32_t lid[KV + 4];
+        T val[KV + 4];
+#pragma unroll
+        for (int k = 0; k < KV; ++k) {
+            act[k] = in && k < n_in && r.lid[k] != kNoLayer;
+            lid[k] = r.lid[k];
+            val[k] = r.val[k];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            act[KV + j] = in && j < cnt;
+            lid[KV + j] = (s.ob[v].lid4 >> (8 * j)) & 0xffu;
+            val[KV + j] = s.ob[v].val[j];
+        }
+        add_distinct<T, KV + 4>(acc, lane, act, lid, val);
+        // further blocks (an event in more than KV + 3 layers)
+        for (int i0 = 4; i0 < (in ? cnt : 0); i0 += 4) {
+            OvBlock<T> o;
+            load_ov_block(b, pos + (uint32_t)i0, o);
+            bool a2[4];
+            uint32_t l2[4];
+            T v2[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                a2[j] = i0 + j < cnt;
+                l2[j] = (o.lid4 >> (8 * j)) & 0xffu;
+                v2[j] = o.val[j];
+            }
+            add_distinct<T, 4>(acc, lane, a2, l2, v2);
+        }
+    }
+}
+
+// Year losses of the trial in the accumulators (lane l: layer l, folded in
+// the butterfly order of wave_allreduce), then the accumulators cleared.
+template <typename T>
+__device__ __forceinline__ void batch_finish_trial(Acc<T> *acc, int lane, int n_layers, int64_t trial, double *my_ylt,
+                                                   double my_ret, double my_lim) {
+    wave_lds_fence();
+    if (lane < n_layers) {
+        const Acc<T> *row = acc + lane * kAccStride;
+        Acc<T> v[kWave / 2];
+#pragma unroll
+        for (int i = 0; i < kWave / 2; ++i) v[i] = Acc<T>::combine(row[i], row[i + kWave / 2]);
+#pragma unroll
+        for (int m = kWave / 4; m >= 1; m >>= 1)
+#pragma unroll
+            for (int i = 0; i < m; ++i) v[i] = Acc<T>::combine(v[i], v[i + m]);
+        my_ylt[trial] = clamp_excess(v[0].value(), my_ret, my_lim);
+    }
+    wave_lds_fence();
+    for (int l = 0; l < n_layers; ++l) acc[l * kAccStride + lane] = Acc<T>::zero();
+}
+
+template <typename T, bool FIXED, bool ALIGNED>
+__device__ __forceinline__ void stream_step(const YetView &y, const int64_t *__restrict__ off, const BatchTables &b,
+                                            const Record<T> *__restrict__ rec, ChunkCursor &cc, int64_t n_waves,
+                                            int lane, int64_t last_granule, Acc<T> *acc, double *my_ylt,
+                                            double my_ret, double my_lim, StreamSlot<T> &s0, StreamSlot<T> &s1,
+                                            StreamSlot<T> &s2) {
+    stream_heads(b, s1);
+    stream_records(rec, s2);
+    stream_next<T, FIXED, ALIGNED>(y, off, cc, n_waves, lane, last_granule, s0);
+    stream_add(b, s0, acc, lane);
+    if (s0.last) batch_finish_trial(acc, lane, b.n_layers, s0.trial, my_ylt, my_ret, my_lim);
+}
+
+template <typename T, bool FIXED, bool ALIGNED>
+__global__ __launch_bounds__(256) void k_trial_pass_batch_stream(YetView y, const int64_t *__restrict__ off,
+                                                                 BatchTables b) {
+    extern __shared__ uint64_t lds_raw[];
+    const int lane = lane_id();
+    const int n_layers = b.n_layers;
+    Acc<T> *acc = reinterpret_cast<Acc<T> *>(lds_raw) + (size_t)(threadIdx.x >> 6) * n_layers * kAccStride;
+    const Record<T> *__restrict__ rec = static_cast<const Record<T> *>(b.rec);
+    double *my_ylt = nullptr;
+    double my_ret = 0.0, my_lim = 0.0;
+    if (lane < n_layers) {
+        my_ylt = b.ylts[lane];
+        my_ret = b.agg_ret[lane];
+        my_lim = b.agg_lim[lane];
+    }
+    for (int l = 0; l < n_layers; ++l) acc[l * kAccStride + lane] = Acc<T>::zero();
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t last_granule = (y.n_events - 1) & ~3LL;  // launched only with n_events >= 1
+    ChunkCursor cc;
+    cc.trial = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    cc.base = 0;
+    cc.r = TrialRange{0, 0};
+    cursor_enter<FIXED>(y, off, cc);
+    StreamSlot<T> A, B, C;
+    // prologue: chunk 0 in A up to its overflow blocks, chunk 1 in B up to
+    // its records, chunk 2's IDs in C
+    stream_next<T, FIXED, ALIGNED>(y, off, cc, n_waves, lane, last_granule, A);
+    stream_next<T, FIXED, ALIGNED>(y, off, cc, n_waves, lane, last_granule, B);
+    stream_records(rec, A);
+    stream_next<T, FIXED, ALIGNED>(y, off, cc, n_waves, lane, last_granule, C);
+    stream_records(rec, B);
+    stream_heads(b, A);
+    while (true) {
+        if (A.trial < 0) break;
+        stream_step<T, FIXED, ALIGNED>(y, off, b, rec, cc, n_waves, lane, last_granule, acc, my_ylt, my_ret, my_lim, A, B, C);
+        if (B.trial < 0) break;
+        stream_step<T, FIXED, ALIGNED>(y, off, b, rec, cc, n_waves, lane, last_granule, acc, my_ylt, my_ret, my_lim, B, C, A);
+        if (C.trial < 0) break;
+        stream_step<T, FIXED, ALIGNED>(y, off, b, rec, cc, n_waves, lane, last_granule, acc, my_ylt, my_ret, my_lim, C, A, B);
     }
 }
 
@@ -1536,13 +1821,23 @@ auto batch_kernel(bool fixed, bool aligned) {
 }
 
 template <typename T>
+auto batch_stream_kernel(bool fixed, bool aligned) {
+    return fixed ? &k_trial_pass_batch_stream<T, true, true>
+                 : (aligned ? &k_trial_pass_batch_stream<T, false, true> : &k_trial_pass_batch_stream<T, false, false>);
+}
+
+template <typename T>
 hipError_t batch_pass_t(const YetView &y, const BatchTables &b, const BatchLaunch &cfg, hipStream_t s) {
     if (y.n_trials == 0) return hipSuccess;
     const bool fixed = y.offsets == nullptr && y.aligned16 && y.events_per_trial > 0 && (y.events_per_trial % 4) == 0;
     const bool al = y.aligned16 != 0;
-    if (cfg.group != 2 && cfg.group != 4 && cfg.group != 8) return hipErrorInvalidValue;
-    auto kern = cfg.group == 2 ? batch_kernel<T, 2>(fixed, al)
-                               : (cfg.group == 8 ? batch_kernel<T, 8>(fixed, al) : batch_kernel<T, 4>(fixed, al));
+    if (cfg.group != 1 && cfg.group != 2 && cfg.group != 4 && cfg.group != 8) return hipErrorInvalidValue;
+    // group 1: the pipelined pass (256-thread work-groups at most)
+    if (cfg.group == 1 && cfg.threads > kMaxStreamThreads) return hipErrorInvalidValue;
+    auto kern = cfg.group == 1 ? batch_stream_kernel<T>(fixed, al)
+                               : (cfg.group == 2 ? batch_kernel<T, 2>(fixed, al)
+                                                 : (cfg.group == 8 ? batch_kernel<T, 8>(fixed, al)
+                                                                   : batch_kernel<T, 4>(fixed, al)));
     const size_t lds = batch_lds_bytes(b.n_layers, cfg.threads);
     if (lds > 160u * 1024u || cfg.threads < kWave || cfg.threads > 512 || cfg.threads % kWave) return hipErrorInvalidValue;
     hipError_t ae = allow_dynamic_lds(reinterpret_cast<const void *>(kern), 160 * 1024);

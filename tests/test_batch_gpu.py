@@ -51,10 +51,28 @@ CASES = [
 ]
 
 
+# Pass forms of sparse batches: the tuner's choice, or forced: the grouped
+# pass (8 chunks per step) and the pipelined pass (one chunk per step, loads
+# staged over three steps).  Batches of up to 16 layers take the dense form
+# whatever the force (the dense passes have their own tests below).
+FORMS = {"tuned": None, "grouped": "256,1,8", "pipelined": "256,1,1"}
+
+
+def _force(monkeypatch, form):
+    if FORMS[form]:
+        monkeypatch.setenv("ARA_BATCH_LAUNCH", FORMS[form])
+    else:
+        monkeypatch.delenv("ARA_BATCH_LAUNCH", raising=False)
+
+
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_batch_equals_single_layer_passes(case, prec):
+def test_batch_equals_single_layer_passes(case, prec, form, monkeypatch):
     name, T, L_, C, n, max_j, esz, fixed, mis = case
+    if form != "tuned" and n <= 16:
+        pytest.skip("dense form: the forced shape does not apply")
+    _force(monkeypatch, form)
     if fixed:
         rng = np.random.default_rng(T)
         K = int(L_)
@@ -72,7 +90,9 @@ def test_batch_equals_single_layer_passes(case, prec):
     torch.cuda.synchronize()
     threads, per_cu = batch.launch_config
     assert threads % 64 == 0 and per_cu >= 1
-    assert batch.launch_group in (2, 4, 8)
+    assert batch.launch_group in (1, 2, 4, 8)
+    if form != "tuned":
+        assert (threads, per_cu, batch.launch_group) == tuple(int(x) for x in FORMS[form].split(","))
     for l in range(n):
         assert np.array_equal(outs[l].cpu().numpy(), singles[l]), (name, l)
     # a second run (graph replay) into new buffers gives the same bits
@@ -86,9 +106,12 @@ def test_batch_equals_single_layer_passes(case, prec):
         assert_close_to_oracle(singles[l], ref, prec)
 
 
-def test_batch_overflow_records():
+@pytest.mark.parametrize("form", list(FORMS))
+def test_batch_overflow_records(form, monkeypatch):
     """Dense ELTs over a small catalogue: most events sit in more layers than a
-    record holds inline, so the overflow entries carry most of the losses."""
+    record holds inline, so the overflow entries carry most of the losses
+    (several blocks of four per event)."""
+    _force(monkeypatch, form)
     T, C = 800, 500
     ids, off, _ = W.random_case(77, T, 60.0, C, 1, 1)
     specs = []
@@ -249,14 +272,25 @@ def test_batch_tuned_shape_fits_every_layer_count(monkeypatch):
     b = A.Batch(yet, layers[:33])
     outs = b.run()
     assert b.launch_config == (512, 1) and b.launch_group == 8
-    monkeypatch.delenv("ARA_BATCH_LAUNCH")
-    b.rebuild(layers)
+    b.rebuild(layers)  # the forced shape, narrowed for 64 layers
     outs64 = b.run()
     threads, _ = b.launch_config
     assert threads <= 256
     torch.cuda.synchronize()
     for l in range(33):
         assert np.array_equal(outs[l].cpu().numpy(), singles[l])
+    for l in range(64):
+        assert np.array_equal(outs64[l].cpu().numpy(), singles[l])
+    b.close()
+    # a tuned shape remembered for 33 layers, reused (narrowed if needed) for 64
+    monkeypatch.delenv("ARA_BATCH_LAUNCH")
+    b = A.Batch(yet, layers[:33])
+    b.run()
+    b.rebuild(layers)
+    outs64 = b.run()
+    threads, per_cu = b.launch_config
+    assert (threads // 64) * 64 * 65 * 8 <= 160 * 1024
+    torch.cuda.synchronize()
     for l in range(64):
         assert np.array_equal(outs64[l].cpu().numpy(), singles[l])
     b.close()
