@@ -46,12 +46,14 @@ struct TablesView {
     const uint2 *bm;
     const void *rows;
     // FUSED: occ[catalog + 1] occurrence loss of every event (occ[catalog] = 0);
-    // bit b of filt[w] is
-    // set iff an event of block 32w+b (a block being 2^fshift consecutive
-    // events) has a non-zero occurrence loss.  When fshift > 0 a second,
-    // hashed filter follows in filt[n_fwords .. n_fwords + n_hwords): bit
-    // ((E mod 2^24) * kHashMul24 mod 2^32) >> hshift is set for every event E
-    // with a non-zero occurrence loss (n_hwords = 0: none).
+    // event E maps to bit E mod 32 of filt[E >> (fshift + 5)], which is set
+    // iff one of the 2^fshift events sharing it (E + 32 t inside the word's
+    // 2^(fshift + 5) events) has a non-zero occurrence loss.  When fshift > 0
+    // a second, hashed filter follows in filt[n_fwords .. n_fwords +
+    // n_hwords): bit E mod 32 of word ((E mod 2^24) * kHashMul24 mod 2^32)
+    // >> (hshift + 5) is set for every event E with a non-zero occurrence
+    // loss (n_hwords = 0: none).  A probe is one LDS word and a bit-field
+    // extract at the ID's own low five bits.
     const void *occ;
     const uint32_t *filt;
     int32_t n_fwords;

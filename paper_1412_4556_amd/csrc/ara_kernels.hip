@@ -99,12 +99,13 @@ struct EventSum<float> {
 // cross-lane moves
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
-// Bit of the hashed filter for an event ID: the top 32 - hshift bits of the
-// low 32 bits of a full-rate 24 x 24-bit product.  __umul24 returns a signed
-// int: the product is taken as unsigned before the shift, so the slot stays
-// below 2^(32 - hshift), the filter's size in bits.
-__device__ __forceinline__ uint32_t hash_slot(uint32_t id, int32_t hshift) {
-    return (uint32_t)__umul24(id, kHashMul24) >> hshift;
+// Word of the hashed filter for an event ID: the top 27 - hshift bits of the
+// low 32 bits of a full-rate 24 x 24-bit product (the event's bit in that
+// word is ID mod 32).  __umul24 returns a signed int: the product is taken
+// as unsigned before the shift, so the word stays below 2^(27 - hshift),
+// the filter's size in words.
+__device__ __forceinline__ uint32_t hash_word(uint32_t id, int32_t hshift) {
+    return (uint32_t)__umul24(id, kHashMul24) >> (hshift + 5);
 }
 
 template <int CTRL, int ROW_MASK>
@@ -499,33 +500,159 @@ __device__ __forceinline__ void load_filters(const FusedFilter &f, uint32_t *sfi
     __syncthreads();
 }
 
+// Lane mask of bit b of w: all ones if set, else 0 (one signed bit-field
+// extract; only the low five bits of b count).
+__device__ __forceinline__ uint32_t bit_mask(uint32_t w, uint32_t b) {
+    return (uint32_t)__builtin_amdgcn_sbfe((int)w, b, 1u);
+}
+
 // Occurrence losses of a group: LDS filter probes per event, then a gather
 // for every event -- of occ[E] where E passes the filters, else of the zero
 // at occ[catalog] -- so no load sits under a branch.  The block filter has
 // no false negatives, and neither has the hashed one (HASH), so an event
-// that fails either has occ[E] = 0.
-template <typename T, bool HASH, int G = kGroup>
+// that fails either has occ[E] = 0.  Each probe and the in-trial bit give a
+// lane mask; the gathered index is the ID under their conjunction, else the
+// zero slot.  WHOLE: the in-trial bits of a chunk are all set or all clear
+// (fixed-length trials).  OFF32: every byte offset into the table fits in
+// 32 bits (a gather is then the table's base plus a 32-bit offset).
+template <typename T, bool HASH, bool WHOLE, int G = kGroup, bool OFF32 = false>
 __device__ __forceinline__ void gather_group(const IdGroupT<G> &g, uint32_t valid, const uint32_t *sfilt,
                                              const FusedFilter &f, int32_t zero_slot, const T *__restrict__ occ,
                                              T (&o)[G][4]) {
     const uint32_t *shash = sfilt + f.n_fwords;
-    int32_t idx[G][4];
+    uint32_t idx[G][4];
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+        const uint32_t cm = bit_mask(valid, 4u * c);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint32_t id = (uint32_t)g.id[c][v];
+            uint32_t m = bit_mask(sfilt[id >> (f.fshift + 5)], id) & (WHOLE ? cm : bit_mask(valid, 4u * c + v));
+            if (HASH) m &= bit_mask(shash[hash_word(id, f.hshift)], id);
+            idx[c][v] = (id & m) | ((uint32_t)zero_slot & ~m);
+        }
+    }
 #pragma unroll
     for (int c = 0; c < G; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const uint32_t blk = (uint32_t)g.id[c][v] >> f.fshift;
-            uint32_t hit = ((valid >> (4 * c + v)) & 1u) & __builtin_amdgcn_ubfe(sfilt[blk >> 5], blk, 1u);
-            if (HASH) {
-                const uint32_t h = hash_slot((uint32_t)g.id[c][v], f.hshift);
-                hit &= __builtin_amdgcn_ubfe(shash[h >> 5], h, 1u);
-            }
-            idx[c][v] = hit ? g.id[c][v] : zero_slot;
+            if (OFF32)
+                o[c][v] = *reinterpret_cast<const T *>(reinterpret_cast<const char *>(occ) +
+                                                       (idx[c][v] * (uint32_t)sizeof(T)));
+            else
+                o[c][v] = occ[idx[c][v]];
         }
+}
+
+// The i-th of a lane's 4G IDs (i < 4G; chunk i / 4, element i % 4), chosen
+// by a binary tree of selects on the bits of i.
+template <int G>
+__device__ __forceinline__ uint32_t select_id(const IdGroupT<G> &g, uint32_t i) {
+    constexpr int N = 4 * G;
+    uint32_t s[N];
 #pragma unroll
-    for (int c = 0; c < G; ++c)
+    for (int k = 0; k < N; ++k) s[k] = (uint32_t)g.id[k >> 2][k & 3];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) o[c][v] = occ[idx[c][v]];
+    for (int n = N / 2, b = 0; n >= 1; n >>= 1, ++b) {
+        const bool hi = ((i >> b) & 1u) != 0u;
+#pragma unroll
+        for (int k = 0; k < n; ++k) s[k] = hi ? s[2 * k + 1] : s[2 * k];
+    }
+    return s[0];
+}
+
+// Gathers of a group, compacted per lane: the filter probes give each lane a
+// mask of its events that pass (bit 4c + v, the lane's event order); the
+// lane then gathers only those, its first kHits of them in kHits gather
+// instructions (the zero slot where it has fewer), the rest one at a time
+// while any lane of the wave has some left.  They are added to acc in the
+// lane's event order, as the uncompacted form adds every event (the events
+// skipped would add exact zeros), so the sums are bitwise the same.  OMAX:
+// their largest into mx.
+template <int G>
+struct CompactHits;
+template <>
+struct CompactHits<1> {
+    static constexpr int k = 2;
+};
+template <>
+struct CompactHits<2> {
+    static constexpr int k = 3;
+};
+template <>
+struct CompactHits<4> {
+    static constexpr int k = 4;
+};
+template <>
+struct CompactHits<8> {
+    static constexpr int k = 6;
+};
+
+template <typename T, bool OFF32>
+__device__ __forceinline__ T gather_one(const T *__restrict__ occ, uint32_t idx) {
+    if (OFF32) return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(occ) + idx * (uint32_t)sizeof(T));
+    return occ[idx];
+}
+
+// Phase one: the probes, the lane's mask of passing events and its first
+// kHits gathers (issued, not waited for).
+template <typename T, int G>
+struct HitGathers {
+    T x[CompactHits<G>::k];
+    uint32_t pass;  // passing events not yet gathered
+};
+
+template <typename T, bool HASH, bool WHOLE, int G, bool OFF32>
+__device__ __forceinline__ void gather_hits(const IdGroupT<G> &g, uint32_t valid, const uint32_t *sfilt,
+                                            const FusedFilter &f, int32_t zero_slot, const T *__restrict__ occ,
+                                            HitGathers<T, G> &h) {
+    static_assert(4 * G <= 32, "one mask bit per event of a lane");
+    const uint32_t *shash = sfilt + f.n_fwords;
+    uint32_t pass = 0;
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+        const uint32_t cm = bit_mask(valid, 4u * c);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint32_t id = (uint32_t)g.id[c][v];
+            uint32_t m = bit_mask(sfilt[id >> (f.fshift + 5)], id) & (WHOLE ? cm : bit_mask(valid, 4u * c + v));
+            if (HASH) m &= bit_mask(shash[hash_word(id, f.hshift)], id);
+            pass |= m & (1u << (4 * c + v));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < CompactHits<G>::k; ++k) {
+        const uint32_t i = (uint32_t)__builtin_ctz(pass | (1u << (4 * G))) & (4 * G - 1);
+        h.x[k] = gather_one<T, OFF32>(occ, pass ? select_id<G>(g, i) : (uint32_t)zero_slot);
+        pass &= pass - 1u;
+    }
+    h.pass = pass;
+}
+
+template <typename T, bool OMAX>
+__device__ __forceinline__ void add_hit(T x, Acc<T> &acc, T &mx) {
+    if (sizeof(T) == 8) {
+        acc.add(x);
+    } else if (x != T(0)) {
+        acc.add(x);
+    }
+    if (OMAX) mx = x > mx ? x : mx;
+}
+
+// Phase two: the sums in the lane's event order, then the lane's remaining
+// passing events one gather at a time while any lane of the wave has some.
+template <typename T, int G, bool OFF32, bool OMAX>
+__device__ __forceinline__ void sum_hits(const IdGroupT<G> &g, HitGathers<T, G> &h, int32_t zero_slot,
+                                         const T *__restrict__ occ, Acc<T> &acc, T &mx) {
+#pragma unroll
+    for (int k = 0; k < CompactHits<G>::k; ++k) add_hit<T, OMAX>(h.x[k], acc, mx);
+    uint32_t pass = h.pass;
+    while (__builtin_amdgcn_ballot_w64(pass != 0u)) {
+        const uint32_t i = (uint32_t)__builtin_ctz(pass | (1u << (4 * G))) & (4 * G - 1);
+        const T x = gather_one<T, OFF32>(occ, pass ? select_id<G>(g, i) : (uint32_t)zero_slot);
+        pass &= pass - 1u;
+        add_hit<T, OMAX>(x, acc, mx);
+    }
 }
 
 // Adds in k_trial_pass order; adding an exact zero changes no bit of the sum.
@@ -561,8 +688,57 @@ __device__ __forceinline__ TrialRange fused_range(const YetView &y, const int64_
     return TrialRange{off[i], off[i + 1]};
 }
 
-// OMAX: also the largest occurrence loss of each trial, into omax.
-template <typename T, bool FIXED, bool ALIGNED, bool HASH, int G, bool OMAX>
+// One trial of k_trial_pass_fused: its first group's IDs are in cur; the
+// next trial's range and first group are loaded into rn / nxt on the way.
+// Returns the next trial.
+template <typename T, bool FIXED, bool ALIGNED, bool HASH, int G, bool OMAX, bool OFF32>
+__device__ __forceinline__ int64_t fused_trial(const YetView &y, const int64_t *__restrict__ off, const FusedFilter &f,
+                                               const uint32_t *sfilt, int32_t zero_slot, const T *__restrict__ occ,
+                                               double agg_ret, double agg_lim, double *__restrict__ ylt,
+                                               double *__restrict__ omax, int64_t trial, int64_t n_waves, int lane,
+                                               int64_t last_granule, const TrialRange &r, const IdGroupT<G> &cur,
+                                               uint32_t cur_valid, TrialRange &rn, IdGroupT<G> &nxt,
+                                               uint32_t &nxt_valid) {
+    constexpr int64_t kSpan = (int64_t)G * 4 * kWave;
+    // gathers of this trial first, then the IDs of the next trial, so
+    // that waiting for the gathers does not wait for the prefetch
+    HitGathers<T, G> hits;
+    gather_hits<T, HASH, FIXED, G, OFF32>(cur, cur_valid, sfilt, f, zero_slot, occ, hits);
+    // the last round of a wave loads its own last trial again (unused)
+    const int64_t next = trial + n_waves;
+    const int64_t pre = next < y.n_trials ? next : trial;
+    rn = fused_range<FIXED>(y, off, pre);
+    nxt_valid = load_group<FIXED, ALIGNED, G>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
+    Acc<T> acc = Acc<T>::zero();
+    T m = T(0);
+    sum_hits<T, G, OFF32, OMAX>(cur, hits, zero_slot, occ, acc, m);
+    // the rest of a longer trial: whole groups for fixed-length trials,
+    // single chunks for variable-length ones (a Poisson(1000) trial
+    // exceeds a group by less than a chunk or two; a second group of
+    // registers would also cost occupancy-relevant VGPRs); each lane
+    // still adds its chunks in increasing order
+    constexpr int TG = FIXED ? G : 1;
+    for (int64_t base = chunk_start(y, r.b) + kSpan; base < r.e; base += (int64_t)TG * 4 * kWave) {
+        IdGroupT<TG> more;
+        const uint32_t mv = load_group<FIXED, ALIGNED, TG>(y, r, base, lane, last_granule, more);
+        HitGathers<T, TG> mh;
+        gather_hits<T, HASH, FIXED, TG, OFF32>(more, mv, sfilt, f, zero_slot, occ, mh);
+        sum_hits<T, TG, OFF32, OMAX>(more, mh, zero_slot, occ, acc, m);
+    }
+    const double S = wave_allreduce(acc).value();
+    if (lane == 0) ylt[trial] = clamp_excess(S, agg_ret, agg_lim);
+    if (OMAX) {
+        m = wave_max(m);
+        if (lane == 0) omax[trial] = (double)m;
+    }
+    return next;
+}
+
+// OMAX: also the largest occurrence loss of each trial, into omax.  A
+// wave's trials alternate between two sets of ID registers (the one being
+// summed, the one being prefetched), so no IDs are copied between trials.
+// OFF32: (catalog + 1) * sizeof(T) <= 2^32.
+template <typename T, bool FIXED, bool ALIGNED, bool HASH, int G, bool OMAX, bool OFF32>
 __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int64_t *__restrict__ off, FusedFilter f,
                                                            int32_t zero_slot, const T *__restrict__ occ,
                                                            double agg_ret, double agg_lim,
@@ -571,55 +747,23 @@ __global__ __launch_bounds__(1024) void k_trial_pass_fused(YetView y, const int6
     load_filters(f, sfilt);
     const int lane = lane_id();
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    constexpr int64_t kSpan = (int64_t)G * 4 * kWave;
     const int64_t last_granule = (y.n_events - 1) & ~3LL;  // launched only with n_events >= 1
     int64_t trial = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
-    TrialRange r{0, 0};
-    IdGroupT<G> cur;
-    uint32_t cur_valid = 0;
+    TrialRange r0{0, 0}, r1{0, 0};
+    IdGroupT<G> g0, g1;
+    uint32_t v0 = 0, v1 = 0;
     if (trial < y.n_trials) {
-        r = fused_range<FIXED>(y, off, trial);
-        cur_valid = load_group<FIXED, ALIGNED, G>(y, r, chunk_start(y, r.b), lane, last_granule, cur);
+        r0 = fused_range<FIXED>(y, off, trial);
+        v0 = load_group<FIXED, ALIGNED, G>(y, r0, chunk_start(y, r0.b), lane, last_granule, g0);
     }
     while (trial < y.n_trials) {
-        // gathers of this trial first, then the IDs of the next trial, so
-        // that waiting for the gathers does not wait for the prefetch
-        T o[G][4];
-        gather_group<T, HASH, G>(cur, cur_valid, sfilt, f, zero_slot, occ, o);
-        // the last round of a wave loads its own last trial again (unused)
-        const int64_t next = trial + n_waves;
-        const int64_t pre = next < y.n_trials ? next : trial;
-        const TrialRange rn = fused_range<FIXED>(y, off, pre);
-        IdGroupT<G> nxt;
-        const uint32_t nxt_valid = load_group<FIXED, ALIGNED, G>(y, rn, chunk_start(y, rn.b), lane, last_granule, nxt);
-        Acc<T> acc = Acc<T>::zero();
-        accumulate_group(o, acc);
-        T m = T(0);
-        if (OMAX) max_group(o, m);
-        // the rest of a longer trial: whole groups for fixed-length trials,
-        // single chunks for variable-length ones (a Poisson(1000) trial
-        // exceeds a group by less than a chunk or two; a second group of
-        // registers would also cost occupancy-relevant VGPRs); each lane
-        // still adds its chunks in increasing order
-        constexpr int TG = FIXED ? G : 1;
-        for (int64_t base = chunk_start(y, r.b) + kSpan; base < r.e; base += (int64_t)TG * 4 * kWave) {
-            IdGroupT<TG> more;
-            const uint32_t mv = load_group<FIXED, ALIGNED, TG>(y, r, base, lane, last_granule, more);
-            T ot[TG][4];
-            gather_group<T, HASH, TG>(more, mv, sfilt, f, zero_slot, occ, ot);
-            accumulate_group<T, TG>(ot, acc);
-            if (OMAX) max_group<T, TG>(ot, m);
-        }
-        const double S = wave_allreduce(acc).value();
-        if (lane == 0) ylt[trial] = clamp_excess(S, agg_ret, agg_lim);
-        if (OMAX) {
-            m = wave_max(m);
-            if (lane == 0) omax[trial] = (double)m;
-        }
-        trial = next;
-        r = rn;
-        cur = nxt;
-        cur_valid = nxt_valid;
+        trial = fused_trial<T, FIXED, ALIGNED, HASH, G, OMAX, OFF32>(y, off, f, sfilt, zero_slot, occ, agg_ret, agg_lim, ylt,
+                                                              omax, trial, n_waves, lane, last_granule, r0, g0, v0,
+                                                              r1, g1, v1);
+        if (trial >= y.n_trials) break;
+        trial = fused_trial<T, FIXED, ALIGNED, HASH, G, OMAX, OFF32>(y, off, f, sfilt, zero_slot, occ, agg_ret, agg_lim, ylt,
+                                                              omax, trial, n_waves, lane, last_granule, r1, g1, v1,
+                                                              r0, g0, v0);
     }
 }
 
@@ -649,7 +793,7 @@ __global__ __launch_bounds__(1024) void k_trial_pass_events_fused(
     }
     while (trial < y.n_trials) {
         T o[G][4];
-        gather_group<T, HASH, G>(cur, cur_valid, sfilt, f, zero_slot, occ, o);
+        gather_group<T, HASH, FIXED, G>(cur, cur_valid, sfilt, f, zero_slot, occ, o);
         const int64_t next = trial + n_waves;
         const TrialRange rn = fused_range<FIXED>(y, off, next < y.n_trials ? next : trial);
         IdGroupT<G> nxt;
@@ -715,7 +859,7 @@ __global__ __launch_bounds__(1024) void k_trial_pass_events_fused(
             if (base >= r.e) break;
             IdGroupT<G> more;
             valid = load_group<FIXED, ALIGNED, G>(y, r, base, lane, last_granule, more);
-            gather_group<T, HASH, G>(more, valid, sfilt, f, zero_slot, occ, o);
+            gather_group<T, HASH, FIXED, G>(more, valid, sfilt, f, zero_slot, occ, o);
         }
         if (lane == 0) ylt[trial] = clamp_excess(carry.value(), agg_ret, agg_lim);
         trial = next;
@@ -1281,10 +1425,9 @@ __global__ __launch_bounds__(256) void k_dense_fill(OccPtrs occ, int32_t n_layer
             any |= v != T(0) ? 1u : 0u;
         }
         if (e <= catalog) rec[e] = r;
-        const int64_t blk = e >> fshift;
-        const int64_t w = blk >> 5;
-        const int64_t w_first = (base >> fshift) >> 5;
-        const uint32_t bit = any ? 1u << (uint32_t)(blk & 31) : 0u;
+        const int64_t w = e >> (fshift + 5);
+        const int64_t w_first = base >> (fshift + 5);
+        const uint32_t bit = any ? 1u << (uint32_t)(e & 31) : 0u;
         uint32_t lo = w == w_first ? bit : 0u, hi = w == w_first ? 0u : bit;
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) {
@@ -1295,10 +1438,7 @@ __global__ __launch_bounds__(256) void k_dense_fill(OccPtrs occ, int32_t n_layer
         if (lane == 0 && hi) atomicOr(&filt[w_first + 1], hi);
         const unsigned long long members = __ballot(any != 0u);
         if (lane == 0 && members) atomicAdd(union_count, (unsigned long long)__popcll(members));
-        if (n_hwords > 0 && any) {
-            const uint32_t h = hash_slot((uint32_t)e, hshift);
-            atomicOr(&hwords[h >> 5], 1u << (h & 31u));
-        }
+        if (n_hwords > 0 && any) atomicOr(&hwords[hash_word((uint32_t)e, hshift)], 1u << (uint32_t)(e & 31));
     }
 }
 
@@ -1312,13 +1452,10 @@ __device__ __forceinline__ void filter_group(const IdGroupT<G> &g, uint32_t vali
     for (int c = 0; c < G; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const uint32_t blk = (uint32_t)g.id[c][v] >> f.fshift;
-            uint32_t hit = ((valid >> (4 * c + v)) & 1u) & __builtin_amdgcn_ubfe(sfilt[blk >> 5], blk, 1u);
-            if (HASH) {
-                const uint32_t h = hash_slot((uint32_t)g.id[c][v], f.hshift);
-                hit &= __builtin_amdgcn_ubfe(shash[h >> 5], h, 1u);
-            }
-            idx[c][v] = hit ? g.id[c][v] : zero_slot;
+            const uint32_t id = (uint32_t)g.id[c][v];
+            uint32_t m = bit_mask(sfilt[id >> (f.fshift + 5)], id) & bit_mask(valid, 4u * c + v);
+            if (HASH) m &= bit_mask(shash[hash_word(id, f.hshift)], id);
+            idx[c][v] = (int32_t)((id & m) | ((uint32_t)zero_slot & ~m));
         }
 }
 
@@ -1463,16 +1600,9 @@ __global__ void k_build_filter(const T *__restrict__ occ, int64_t catalog, int32
                                int32_t n_fwords) {
     for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_fwords; w += (int64_t)gridDim.x * blockDim.x) {
         uint32_t bits = 0;
-        for (int b = 0; b < 32; ++b) {
-            const int64_t lo = ((w << 5) + b) << fshift;
-            int64_t hi = lo + (1LL << fshift);
-            if (hi > catalog) hi = catalog;
-            for (int64_t e = lo; e < hi; ++e)
-                if (occ[e] != T(0)) {
-                    bits |= 1u << b;
-                    break;
-                }
-        }
+        const int64_t lo = w << (fshift + 5);
+        const int64_t hi = lo + (32LL << fshift) < catalog ? lo + (32LL << fshift) : catalog;
+        for (int64_t e = lo; e < hi; ++e) bits |= (occ[e] != T(0) ? 1u : 0u) << (uint32_t)(e & 31);
         filt[w] = bits;
     }
 }
@@ -1482,10 +1612,7 @@ __global__ void k_build_filter(const T *__restrict__ occ, int64_t catalog, int32
 template <typename T>
 __global__ void k_hash_filter(const T *__restrict__ occ, int64_t catalog, int32_t hshift, uint32_t *__restrict__ words) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < catalog; e += (int64_t)gridDim.x * blockDim.x)
-        if (occ[e] != T(0)) {
-            const uint32_t h = hash_slot((uint32_t)e, hshift);
-            atomicOr(&words[h >> 5], 1u << (h & 31u));
-        }
+        if (occ[e] != T(0)) atomicOr(&words[hash_word((uint32_t)e, hshift)], 1u << (uint32_t)(e & 31));
 }
 
 // A layer's fused table in one launch.  Work-group g owns the catalogue
@@ -1573,8 +1700,10 @@ __global__ __launch_bounds__(kBuildThreads) void k_fused_build(const int32_t *__
         hi[k] = o;
     }
     __syncthreads();
-    // block filter words of the range: bit b of word w is set iff an event of
-    // block 32 w + b (2^fshift events) has a non-zero occurrence loss
+    // block filter words of the range: bit b of word w is set iff one of the
+    // events 2^(fshift + 5) w + 32 t + b (t < 2^fshift) has a non-zero
+    // occurrence loss (the range starts on a word: kBuildRange is a multiple
+    // of 2^(fshift + 5), and holds the zero slot's slot as 0)
     const int wshift = 5 + fshift;
     const int64_t w0 = base >> wshift;
     const int n_w = kBuildRange >> wshift;
@@ -1582,22 +1711,16 @@ __global__ __launch_bounds__(kBuildThreads) void k_fused_build(const int32_t *__
         const int64_t w = w0 + q;
         if (w >= n_fwords) continue;
         uint32_t bits = 0;
-        const int per = 1 << fshift;
-        for (int bb = 0; bb < 32; ++bb) {
-            const int k0 = (q << wshift) + (bb << fshift);
-            uint32_t any = 0;
-            for (int t = 0; t < per; ++t) any |= hi[k0 + t] != T(0) ? 1u : 0u;
-            bits |= any << bb;
-        }
+        const int k0 = q << wshift;
+        const int k1 = k0 + (1 << wshift) < (int)nloc ? k0 + (1 << wshift) : (int)nloc;
+        for (int k = k0; k < k1; ++k) bits |= (hi[k] != T(0) ? 1u : 0u) << (uint32_t)(k & 31);
         filt[w] = bits;
     }
     if (n_hwords > 0) {
         for (uint32_t k = threadIdx.x; k < nloc; k += blockDim.x) {
             const int64_t e = base + k;
-            if (e < catalog && hi[k] != T(0)) {
-                const uint32_t h = hash_slot((uint32_t)e, hshift);
-                atomicOr(&hwords[h >> 5], 1u << (h & 31u));
-            }
+            if (e < catalog && hi[k] != T(0))
+                atomicOr(&hwords[hash_word((uint32_t)e, hshift)], 1u << (uint32_t)(e & 31));
         }
     }
 }
@@ -1671,14 +1794,21 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
                                double *);
         using EventsK = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const T *, double, double, double *,
                                  double *, double *);
-        const PassK pk[12] = {
-            &k_trial_pass_fused<T, true, true, false, 4, false>,  &k_trial_pass_fused<T, false, true, false, 4, false>,
-            &k_trial_pass_fused<T, false, false, false, 4, false>, &k_trial_pass_fused<T, true, true, true, 4, false>,
-            &k_trial_pass_fused<T, false, true, true, 4, false>,  &k_trial_pass_fused<T, false, false, true, 4, false>,
-            &k_trial_pass_fused<T, true, true, false, 4, true>,   &k_trial_pass_fused<T, false, true, false, 4, true>,
-            &k_trial_pass_fused<T, false, false, false, 4, true>, &k_trial_pass_fused<T, true, true, true, 4, true>,
-            &k_trial_pass_fused<T, false, true, true, 4, true>,   &k_trial_pass_fused<T, false, false, true, 4, true>};
-        const int pv = variant + (d_omax ? 6 : 0);
+#define ARA_FUSED_PASSES(O32)                                                                                      \
+    &k_trial_pass_fused<T, true, true, false, 4, false, O32>, &k_trial_pass_fused<T, false, true, false, 4, false, O32>, \
+        &k_trial_pass_fused<T, false, false, false, 4, false, O32>,                                                    \
+        &k_trial_pass_fused<T, true, true, true, 4, false, O32>, &k_trial_pass_fused<T, false, true, true, 4, false, O32>, \
+        &k_trial_pass_fused<T, false, false, true, 4, false, O32>,                                                     \
+        &k_trial_pass_fused<T, true, true, false, 4, true, O32>, &k_trial_pass_fused<T, false, true, false, 4, true, O32>, \
+        &k_trial_pass_fused<T, false, false, false, 4, true, O32>,                                                     \
+        &k_trial_pass_fused<T, true, true, true, 4, true, O32>, &k_trial_pass_fused<T, false, true, true, 4, true, O32>,   \
+        &k_trial_pass_fused<T, false, false, true, 4, true, O32>
+        const PassK pk[24] = {ARA_FUSED_PASSES(false), ARA_FUSED_PASSES(true)};
+#undef ARA_FUSED_PASSES
+        // 32-bit table offsets while every byte of the table (zero slot
+        // included) lies below 2^32
+        const bool off32 = ((int64_t)L.catalog + 1) * (int64_t)sizeof(T) <= (1LL << 32);
+        const int pv = variant + (d_omax ? 6 : 0) + (off32 ? 12 : 0);
         const EventsK ek[6] = {&k_trial_pass_events_fused<T, true, true, false, 4>,
                                &k_trial_pass_events_fused<T, false, true, false, 4>,
                                &k_trial_pass_events_fused<T, false, false, false, 4>,
