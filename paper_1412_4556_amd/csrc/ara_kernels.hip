@@ -602,10 +602,11 @@ struct HitGathers {
     uint32_t pass;  // passing events not yet gathered
 };
 
-template <typename T, bool HASH, bool WHOLE, int G, bool OFF32>
-__device__ __forceinline__ void gather_hits(const IdGroupT<G> &g, uint32_t valid, const uint32_t *sfilt,
-                                            const FusedFilter &f, int32_t zero_slot, const T *__restrict__ occ,
-                                            HitGathers<T, G> &h) {
+// A lane's events of a group that lie in the trial and pass the LDS
+// filters: bit 4c + v for element v of chunk c.
+template <bool HASH, bool WHOLE, int G>
+__device__ __forceinline__ uint32_t pass_mask(const IdGroupT<G> &g, uint32_t valid, const uint32_t *sfilt,
+                                              const FusedFilter &f) {
     static_assert(4 * G <= 32, "one mask bit per event of a lane");
     const uint32_t *shash = sfilt + f.n_fwords;
     uint32_t pass = 0;
@@ -620,10 +621,24 @@ __device__ __forceinline__ void gather_hits(const IdGroupT<G> &g, uint32_t valid
             pass |= m & (1u << (4 * c + v));
         }
     }
+    return pass;
+}
+
+// Position (0 .. 4G - 1) of the lowest set bit of a non-empty mask (0 for
+// an empty one).
+template <int G>
+__device__ __forceinline__ uint32_t first_pass(uint32_t pass) {
+    return (uint32_t)__builtin_ctz(pass | (1u << (4 * G))) & (4 * G - 1);
+}
+
+template <typename T, bool HASH, bool WHOLE, int G, bool OFF32>
+__device__ __forceinline__ void gather_hits(const IdGroupT<G> &g, uint32_t valid, const uint32_t *sfilt,
+                                            const FusedFilter &f, int32_t zero_slot, const T *__restrict__ occ,
+                                            HitGathers<T, G> &h) {
+    uint32_t pass = pass_mask<HASH, WHOLE, G>(g, valid, sfilt, f);
 #pragma unroll
     for (int k = 0; k < CompactHits<G>::k; ++k) {
-        const uint32_t i = (uint32_t)__builtin_ctz(pass | (1u << (4 * G))) & (4 * G - 1);
-        h.x[k] = gather_one<T, OFF32>(occ, pass ? select_id<G>(g, i) : (uint32_t)zero_slot);
+        h.x[k] = gather_one<T, OFF32>(occ, pass ? select_id<G>(g, first_pass<G>(pass)) : (uint32_t)zero_slot);
         pass &= pass - 1u;
     }
     h.pass = pass;
@@ -648,8 +663,7 @@ __device__ __forceinline__ void sum_hits(const IdGroupT<G> &g, HitGathers<T, G> 
     for (int k = 0; k < CompactHits<G>::k; ++k) add_hit<T, OMAX>(h.x[k], acc, mx);
     uint32_t pass = h.pass;
     while (__builtin_amdgcn_ballot_w64(pass != 0u)) {
-        const uint32_t i = (uint32_t)__builtin_ctz(pass | (1u << (4 * G))) & (4 * G - 1);
-        const T x = gather_one<T, OFF32>(occ, pass ? select_id<G>(g, i) : (uint32_t)zero_slot);
+        const T x = gather_one<T, OFF32>(occ, pass ? select_id<G>(g, first_pass<G>(pass)) : (uint32_t)zero_slot);
         pass &= pass - 1u;
         add_hit<T, OMAX>(x, acc, mx);
     }
@@ -1442,45 +1456,68 @@ __global__ __launch_bounds__(256) void k_dense_fill(OccPtrs occ, int32_t n_layer
     }
 }
 
-// LDS filter probes of a group: the record index of every event, that of
-// the all-zero record for events that fail a filter or lie outside the trial.
-template <bool HASH, int G>
-__device__ __forceinline__ void filter_group(const IdGroupT<G> &g, uint32_t valid, const uint32_t *sfilt,
-                                             const FusedFilter &f, int32_t zero_slot, int32_t (&idx)[G][4]) {
-    const uint32_t *shash = sfilt + f.n_fwords;
+// Records of a group's passing events, compacted per lane as in the fused
+// pass (gather_hits / sum_hits): the first kDenseHits in as many gathers
+// (the all-zero record where a lane has fewer), then the rest one at a
+// time while any lane has some.  Every layer's losses are added in the
+// lane's event order, as the single-layer pass adds them (skipped events
+// add exact zeros there; FP32C skips zeros as there).
+template <int G>
+struct DenseHits;
+template <>
+struct DenseHits<1> {
+    static constexpr int k = 3;
+};
+template <>
+struct DenseHits<2> {
+    static constexpr int k = 4;
+};
+template <>
+struct DenseHits<4> {
+    static constexpr int k = 6;
+};
+
+template <typename T, int NL, int G>
+struct HitRecs {
+    DenseRec<T, NL> x[DenseHits<G>::k];
+    uint32_t pass;
+};
+
+template <typename T, int NL, bool HASH, int G>
+__device__ __forceinline__ void gather_recs(const IdGroupT<G> &g, uint32_t valid, const uint32_t *sfilt,
+                                            const FusedFilter &f, int32_t zero_slot,
+                                            const DenseRec<T, NL> *__restrict__ rec, HitRecs<T, NL, G> &h) {
+    uint32_t pass = pass_mask<HASH, false, G>(g, valid, sfilt, f);
 #pragma unroll
-    for (int c = 0; c < G; ++c)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const uint32_t id = (uint32_t)g.id[c][v];
-            uint32_t m = bit_mask(sfilt[id >> (f.fshift + 5)], id) & bit_mask(valid, 4u * c + v);
-            if (HASH) m &= bit_mask(shash[hash_word(id, f.hshift)], id);
-            idx[c][v] = (int32_t)((id & m) | ((uint32_t)zero_slot & ~m));
-        }
+    for (int k = 0; k < DenseHits<G>::k; ++k) {
+        h.x[k] = rec[pass ? select_id<G>(g, first_pass<G>(pass)) : (uint32_t)zero_slot];
+        pass &= pass - 1u;
+    }
+    h.pass = pass;
 }
 
-// Adds the records of a group's events to the per-layer running sums,
-// chunk by chunk and in each chunk the lane's four events in order: for
-// every layer the order of the single-layer pass (FP32C: zeros skipped as
-// there; adding them would change no bit either).
+template <typename T, int NL>
+__device__ __forceinline__ void add_rec(const DenseRec<T, NL> &r, Acc<T> (&acc)[NL]) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        if (sizeof(T) == 8) {
+            acc[l].add(r.v[l]);
+        } else if (r.v[l] != T(0)) {
+            acc[l].add(r.v[l]);
+        }
+    }
+}
+
 template <typename T, int NL, int G>
-__device__ __forceinline__ void add_dense_group(const int32_t (&idx)[G][4], const DenseRec<T, NL> *__restrict__ rec,
-                                                Acc<T> (&acc)[NL]) {
+__device__ __forceinline__ void sum_recs(const IdGroupT<G> &g, HitRecs<T, NL, G> &h, int32_t zero_slot,
+                                         const DenseRec<T, NL> *__restrict__ rec, Acc<T> (&acc)[NL]) {
 #pragma unroll
-    for (int c = 0; c < G; ++c) {
-        DenseRec<T, NL> r[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) r[v] = rec[idx[c][v]];
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int l = 0; l < NL; ++l) {
-                if (sizeof(T) == 8) {
-                    acc[l].add(r[v].v[l]);
-                } else if (r[v].v[l] != T(0)) {
-                    acc[l].add(r[v].v[l]);
-                }
-            }
+    for (int k = 0; k < DenseHits<G>::k; ++k) add_rec<T, NL>(h.x[k], acc);
+    uint32_t pass = h.pass;
+    while (__builtin_amdgcn_ballot_w64(pass != 0u)) {
+        const DenseRec<T, NL> r = rec[pass ? select_id<G>(g, first_pass<G>(pass)) : (uint32_t)zero_slot];
+        pass &= pass - 1u;
+        add_rec<T, NL>(r, acc);
     }
 }
 
@@ -1517,8 +1554,8 @@ __global__ __launch_bounds__(1024) void k_trial_pass_dense(YetView y, const int6
         cur_valid = load_group<FIXED, ALIGNED, G>(y, r, chunk_start(y, r.b), lane, last_granule, cur);
     }
     while (trial < y.n_trials) {
-        int32_t idx[G][4];
-        filter_group<HASH, G>(cur, cur_valid, sfilt, f, zero_slot, idx);
+        HitRecs<T, NL, G> hits;
+        gather_recs<T, NL, HASH, G>(cur, cur_valid, sfilt, f, zero_slot, rec, hits);
         const int64_t next = trial + n_waves;
         const TrialRange rn = fused_range<FIXED>(y, off, next < y.n_trials ? next : trial);
         IdGroupT<G> nxt;
@@ -1526,14 +1563,14 @@ __global__ __launch_bounds__(1024) void k_trial_pass_dense(YetView y, const int6
         Acc<T> acc[NL];
 #pragma unroll
         for (int l = 0; l < NL; ++l) acc[l] = Acc<T>::zero();
-        add_dense_group<T, NL, G>(idx, rec, acc);
+        sum_recs<T, NL, G>(cur, hits, zero_slot, rec, acc);
         constexpr int TG = FIXED ? G : 1;
         for (int64_t base = chunk_start(y, r.b) + kSpan; base < r.e; base += (int64_t)TG * kChunkEvents) {
             IdGroupT<TG> more;
             const uint32_t mv = load_group<FIXED, ALIGNED, TG>(y, r, base, lane, last_granule, more);
-            int32_t mi[TG][4];
-            filter_group<HASH, TG>(more, mv, sfilt, f, zero_slot, mi);
-            add_dense_group<T, NL, TG>(mi, rec, acc);
+            HitRecs<T, NL, TG> mh;
+            gather_recs<T, NL, HASH, TG>(more, mv, sfilt, f, zero_slot, rec, mh);
+            sum_recs<T, NL, TG>(more, mh, zero_slot, rec, acc);
         }
         double mine = 0.0;
 #pragma unroll
