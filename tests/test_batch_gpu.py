@@ -48,6 +48,12 @@ CASES = [
     ("fixed_1000", 600, 1000, 30000, 9, 5, 5000, True, False),
     ("fixed_7_misaligned", 700, 7, 3000, 5, 4, 600, True, True),
     ("empties", 1500, 20.0, 5000, 7, 3, 800, False, False),
+    # sparse records in every YET form (fixed length, misaligned IDs, empty trials)
+    ("fixed_1000_40", 500, 1000, 30000, 40, 5, 3000, True, False),
+    ("fixed_7_20", 600, 7, 3000, 20, 4, 600, True, False),
+    ("fixed_7_misaligned_20", 700, 7, 3000, 20, 4, 600, True, True),
+    ("fixed_12_misaligned_33", 400, 12, 2000, 33, 6, 400, True, True),
+    ("empties_24", 1500, 20.0, 5000, 24, 3, 800, False, False),
 ]
 
 
@@ -80,7 +86,7 @@ def test_batch_equals_single_layer_passes(case, prec, form, monkeypatch):
         off = None
     else:
         K = 0
-        ids, off, _ = W.random_case(T, T, L_, C, 1, 1, empty_frac=0.2 if name == "empties" else 0.0)
+        ids, off, _ = W.random_case(T, T, L_, C, 1, 1, empty_frac=0.2 if name.startswith("empties") else 0.0)
     specs = _layers(hash(name) % 1000, n, C, max_j, esz)
     yet = _yet(ids, off, T, C, K, mis)
     layers = [A.Layer(yet, s, prec, "fused") for s in specs]
