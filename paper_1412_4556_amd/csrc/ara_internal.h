@@ -210,6 +210,10 @@ hipError_t launch_pool_layer(LayerHost &L, const int32_t *d_ids, const void *d_l
 constexpr int kBuildRange = 8192;
 constexpr int kBuildThreads = 1024;
 constexpr int kBuildUnroll = 16;
+// Entries of a range the build lists in LDS before adding them (a range
+// with more takes the ELTs one at a time); a multiple of kBuildThreads, and
+// with the sums it stays within the 160 KiB of LDS.
+constexpr int kBuildList = 4 * kBuildThreads;
 constexpr int64_t kBuildReadBudget = (int64_t)1 << 30;  // IDs read over all work-groups
 struct BuildSegs {
     int64_t begin[kMaxElts];  // ELT j of the layer: entries begin[j] .. begin[j] + count[j]

@@ -624,11 +624,12 @@ __device__ __forceinline__ uint32_t pass_mask(const IdGroupT<G> &g, uint32_t val
     return pass;
 }
 
-// Position (0 .. 4G - 1) of the lowest set bit of a non-empty mask (0 for
-// an empty one).
+// Position (0 .. 4G - 1) of the lowest set bit of a non-empty mask (some
+// position below 4G for an empty one; its lanes gather the zero slot).
 template <int G>
 __device__ __forceinline__ uint32_t first_pass(uint32_t pass) {
-    return (uint32_t)__builtin_ctz(pass | (1u << (4 * G))) & (4 * G - 1);
+    static_assert(4 * G <= 32, "one mask bit per event of a lane");
+    return (uint32_t)__builtin_ctz(pass | 0x80000000u) & (4 * G - 1);
 }
 
 template <typename T, bool HASH, bool WHOLE, int G, bool OFF32>
@@ -1652,21 +1653,114 @@ __global__ void k_hash_filter(const T *__restrict__ occ, int64_t catalog, int32_
         if (occ[e] != T(0)) atomicOr(&words[hash_word((uint32_t)e, hshift)], 1u << (uint32_t)(e & 31));
 }
 
+// Adds entry i of ELT j (at position b + i of the arrays) to its event's
+// sum in LDS: FT1 of its loss, FP32C with a compensation term; CHECK: the
+// loss's validity and a second entry of the same event in ELT j.
+template <typename T, typename LT, bool CHECK>
+__device__ __forceinline__ void build_add(T *hi, float *lo, int *stamp, uint32_t off, LT l, int j, T r, T u,
+                                          int &bad) {
+    if (CHECK) {
+        if (!(l >= LT(0) && l <= __DBL_MAX__)) bad |= 4;
+        if (atomicExch(&stamp[off], j) == j) bad |= 2;
+    }
+    const T x = clamp_excess((T)l, r, u);
+    if (sizeof(T) == sizeof(double)) {
+        hi[off] += x;
+    } else {
+        float sum, err;
+        two_sum((float)hi[off], (float)x, sum, err);
+        hi[off] = (T)sum;
+        lo[off] += err;
+    }
+}
+
+// IDs of one chunk of ELT j (kBuildUnroll per thread, entries i0 + q B +
+// thread), every load unconditional: a chunk wholly inside the ELT reads
+// at 32-bit offsets from the ELT's start, the ELT's last chunk at positions
+// clamped to its last entry.
+__device__ __forceinline__ void build_chunk_ids(const int32_t *__restrict__ ids, const BuildSegs &sg, int j,
+                                                int64_t i0, int32_t (&e)[kBuildUnroll]) {
+    const int64_t b = sg.begin[j], m = sg.count[j];
+    const int32_t *__restrict__ seg = ids + b + i0;  // uniform
+    if (i0 + (int64_t)kBuildUnroll * blockDim.x <= m) {
+#pragma unroll
+        for (int q = 0; q < kBuildUnroll; ++q) e[q] = seg[(uint32_t)(q * blockDim.x + threadIdx.x)];
+    } else {
+        const uint32_t last = (uint32_t)(m - 1 - i0);
+#pragma unroll
+        for (int q = 0; q < kBuildUnroll; ++q) {
+            const uint32_t i = (uint32_t)(q * blockDim.x + threadIdx.x);
+            e[q] = seg[i < last ? i : last];
+        }
+    }
+}
+
+// The scan of a layer's ELTs reads 16-byte granules: ELT j's entries are
+// positions lead_j .. lead_j + m_j - 1 of its granule-aligned span starting
+// at begin_j rounded down to a multiple of four (lead_j = begin_j mod 4).  A
+// chunk is kBuildGranules granules per thread (thread t takes granules
+// c0 / 4 + q B + t); granules past the ELT's last one read that one (the ID
+// arrays are padded to a multiple of four entries and 16-byte aligned).
+constexpr int kBuildGranules = 2;
+struct BuildCursor {
+    int j;       // ELT (sg.n: done)
+    int64_t c0;  // chunk start within the ELT's span (a multiple of 4)
+};
+
+__device__ __forceinline__ int64_t build_span(const BuildSegs &sg, int j) {
+    return (sg.begin[j] & 3) + sg.count[j];
+}
+
+__device__ __forceinline__ void build_first_elt(const BuildSegs &sg, BuildCursor &cc) {
+    while (cc.j < sg.n && sg.count[cc.j] == 0) ++cc.j;
+}
+
+__device__ __forceinline__ void build_next(const BuildSegs &sg, BuildCursor &cc) {
+    cc.c0 += 4LL * kBuildGranules * blockDim.x;
+    if (cc.c0 >= build_span(sg, cc.j)) {
+        cc.c0 = 0;
+        ++cc.j;
+        build_first_elt(sg, cc);
+    }
+}
+
+__device__ __forceinline__ void build_granules(const int32_t *__restrict__ ids, const BuildSegs &sg,
+                                               const BuildCursor &cc, int32_t (&e)[4 * kBuildGranules]) {
+    const int64_t b0 = sg.begin[cc.j] & ~3LL;
+    const int32_t *__restrict__ seg = ids + b0 + cc.c0;  // uniform, 16-byte aligned
+    const uint32_t last = (uint32_t)((build_span(sg, cc.j) - 1 - cc.c0) >> 2);
+#pragma unroll
+    for (int q = 0; q < kBuildGranules; ++q) {
+        const uint32_t g = (uint32_t)(q * blockDim.x + threadIdx.x);
+        const int4 v = *reinterpret_cast<const int4 *>(seg + 4 * (g < last ? g : last));
+        e[4 * q] = v.x;
+        e[4 * q + 1] = v.y;
+        e[4 * q + 2] = v.z;
+        e[4 * q + 3] = v.w;
+    }
+}
+
 // A layer's fused table in one launch.  Work-group g owns the catalogue
-// events [g R, (g + 1) R) (R = kBuildRange) and keeps their sums in LDS: it
-// reads the IDs of every ELT of the layer, in layer order, and adds FT1 of
-// the losses of its own events (an ELT holds an event at most once, so no
-// two threads of one ELT add to the same slot; a barrier separates the
-// ELTs), which is the order of k_pool_add.  It then applies the occurrence
-// terms, writes its range of the table and its words of the block filter
-// (a range covers whole filter words) and sets the hashed filter's bits of
-// its non-zero events (words cleared beforehand).  Bitwise the table of
-// k_pool_zero / k_pool_add / k_pool_finish and the filter kernels.
+// events [g R, (g + 1) R) (R = kBuildRange) and keeps their sums in LDS.  It
+// reads the IDs of every ELT of the layer (the next chunk's loads in flight
+// while a chunk is checked) and lists the entries of its own events in LDS;
+// it then loads their losses together and adds FT1 of them to the sums one
+// ELT after the other (an ELT holds an event at most once, so no two
+// threads of one ELT add to the same slot; a barrier separates the ELTs),
+// which is the order of k_pool_add.  A range holding more than kBuildList
+// entries takes the ELTs one at a time instead, reading each entry's loss
+// as it goes.  It then applies the occurrence terms, writes its range of
+// the table and its words of the block filter (a range covers whole filter
+// words) and sets the hashed filter's bits of its non-zero events (words
+// cleared beforehand).  Bitwise the table of k_pool_zero / k_pool_add /
+// k_pool_finish and the filter kernels.
 // CHECK (ELTs from the host): also validates every entry and reports in
 // *flags: 1 an ID outside [0, catalog), 2 an ID twice in one ELT, 4 a loss
 // that is negative, infinite or NaN (the table is then not used).
 // LT: type of the stored losses (binary64 from the host; the pool's own
 // type for pool layers); the conversion to T is the one the host would do.
+// A list entry: bits 0..39 the entry's position in the arrays, 40..52 its
+// event's offset in the range, 53..57 its ELT.
 template <typename T, typename LT, bool CHECK>
 __global__ __launch_bounds__(kBuildThreads) void k_fused_build(const int32_t *__restrict__ ids,
                                                                const LT *__restrict__ loss, BuildSegs sg,
@@ -1675,8 +1769,12 @@ __global__ __launch_bounds__(kBuildThreads) void k_fused_build(const int32_t *__
                                                                int32_t n_fwords, int32_t fshift,
                                                                uint32_t *__restrict__ hwords, int32_t n_hwords,
                                                                int32_t hshift, int *flags) {
+    static_assert(kBuildRange <= (1 << 13) && kMaxElts <= 32, "list entry fields");
+    constexpr int kPerThread = kBuildList / kBuildThreads;
     extern __shared__ uint64_t build_lds[];
-    T *hi = reinterpret_cast<T *>(build_lds);
+    __shared__ int list_n;
+    uint64_t *list = build_lds;  // [kBuildList]
+    T *hi = reinterpret_cast<T *>(list + kBuildList);
     float *lo = reinterpret_cast<float *>(hi + kBuildRange);  // FP32C: compensation terms
     int *stamp = reinterpret_cast<int *>(lo + (sizeof(T) == sizeof(float) ? kBuildRange : 0));  // CHECK
     const int64_t base = (int64_t)blockIdx.x * kBuildRange;
@@ -1687,45 +1785,90 @@ __global__ __launch_bounds__(kBuildThreads) void k_fused_build(const int32_t *__
         if (sizeof(T) == sizeof(float)) lo[k] = 0.0f;
         if (CHECK) stamp[k] = -1;
     }
+    if (threadIdx.x == 0) list_n = 0;
     __syncthreads();
     int bad = 0;
-    for (int j = 0; j < sg.n; ++j) {
-        const int64_t b = sg.begin[j], m = sg.count[j];
-        const T r = (T)sg.ret[j], u = (T)sg.lim[j];
-        for (int64_t i0 = 0; i0 < m; i0 += (int64_t)kBuildUnroll * blockDim.x) {
-            int32_t e[kBuildUnroll];
+    // the entries of this range, in any order (the next chunk's granules in
+    // flight while one is checked)
+    // (IDs are in [0, catalog) after the check, so e - base fits 32 bits)
+    const uint32_t base32 = (uint32_t)base;
+    auto scan = [&](const BuildCursor &cc, const int32_t(&e)[4 * kBuildGranules]) {
+        const int64_t b0 = sg.begin[cc.j] & ~3LL;
+        const uint32_t lead = (uint32_t)(sg.begin[cc.j] & 3);
+        const int64_t span = build_span(sg, cc.j) - cc.c0;  // positions of the ELT from the chunk's start on
 #pragma unroll
-            for (int q = 0; q < kBuildUnroll; ++q) {
-                const int64_t i = i0 + (int64_t)q * blockDim.x + threadIdx.x;
-                e[q] = i < m ? ids[b + i] : 0;
-            }
+        for (int q = 0; q < kBuildGranules; ++q)
 #pragma unroll
-            for (int q = 0; q < kBuildUnroll; ++q) {
-                const int64_t i = i0 + (int64_t)q * blockDim.x + threadIdx.x;
-                if (i >= m) continue;
-                if (CHECK && (e[q] < 0 || e[q] >= catalog)) {
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t r = 4u * (q * blockDim.x + threadIdx.x) + v;  // position in the chunk
+                const int32_t id = e[4 * q + v];
+                if ((int64_t)r >= span || (cc.c0 == 0 && r < lead)) continue;
+                if (CHECK && (id < 0 || id >= catalog)) {
                     bad |= 1;
                     continue;
                 }
-                const uint32_t off = (uint32_t)((int64_t)e[q] - base);
+                const uint32_t off = (uint32_t)id - base32;
                 if (off >= nloc) continue;
-                const LT l = loss[b + i];
-                if (CHECK) {
-                    if (!(l >= LT(0) && l <= __DBL_MAX__)) bad |= 4;
-                    if (atomicExch(&stamp[off], j) == j) bad |= 2;
-                }
-                const T x = clamp_excess((T)l, r, u);
-                if (sizeof(T) == sizeof(double)) {
-                    hi[off] += x;
-                } else {
-                    float sum, err;
-                    two_sum((float)hi[off], (float)x, sum, err);
-                    hi[off] = (T)sum;
-                    lo[off] += err;
+                const int slot = atomicAdd(&list_n, 1);
+                if (slot < kBuildList)
+                    list[slot] = ((uint64_t)cc.j << 53) | ((uint64_t)off << 40) | (uint64_t)(b0 + cc.c0 + r);
+            }
+    };
+    BuildCursor ca{0, 0};
+    build_first_elt(sg, ca);
+    int32_t ea[4 * kBuildGranules], eb[4 * kBuildGranules];
+    if (ca.j < sg.n) build_granules(ids, sg, ca, ea);
+    while (ca.j < sg.n) {
+        BuildCursor cb = ca;
+        build_next(sg, cb);
+        if (cb.j < sg.n) build_granules(ids, sg, cb, eb);
+        scan(ca, ea);
+        if (cb.j >= sg.n) break;
+        ca = cb;
+        build_next(sg, ca);
+        if (ca.j < sg.n) build_granules(ids, sg, ca, ea);
+        scan(cb, eb);
+    }
+    __syncthreads();
+    const int n_list = list_n;
+    if (n_list <= kBuildList) {
+        // their losses together, then the sums in layer order
+        uint64_t le[kPerThread];
+        LT lv[kPerThread];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const int sl = threadIdx.x + k * blockDim.x;
+            le[k] = sl < n_list ? list[sl] : ~0ull;
+            lv[k] = LT(0);
+            if (sl < n_list) lv[k] = loss[(int64_t)(le[k] & ((1ull << 40) - 1))];
+        }
+        for (int jj = 0; jj < sg.n; ++jj) {
+            const T r = (T)sg.ret[jj], u = (T)sg.lim[jj];
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k)
+                if ((int)(le[k] >> 53) == jj)
+                    build_add<T, LT, CHECK>(hi, lo, stamp, (uint32_t)(le[k] >> 40) & 0x1fffu, lv[k], jj, r, u, bad);
+            __syncthreads();
+        }
+    } else {
+        // a crowded range: one ELT at a time
+        for (int jj = 0; jj < sg.n; ++jj) {
+            const int64_t b = sg.begin[jj], m = sg.count[jj];
+            const T r = (T)sg.ret[jj], u = (T)sg.lim[jj];
+            for (int64_t ic = 0; ic < m; ic += (int64_t)kBuildUnroll * blockDim.x) {
+                int32_t e[kBuildUnroll];
+                build_chunk_ids(ids, sg, jj, ic, e);
+#pragma unroll 4
+                for (int q = 0; q < kBuildUnroll; ++q) {
+                    const int64_t i = ic + (int64_t)q * blockDim.x + threadIdx.x;
+                    if (i >= m || e[q] < 0 || e[q] >= catalog) continue;  // range errors flagged above
+                    const uint32_t off = (uint32_t)((int64_t)e[q] - base);
+                    if (off >= nloc) continue;
+                    build_add<T, LT, CHECK>(hi, lo, stamp, off, loss[b + i], jj, r, u, bad);
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
     if (CHECK && bad) atomicOr(flags, bad);
     // occurrence terms; the zero slot occ[catalog] stays 0
@@ -2086,7 +2229,8 @@ hipError_t fused_build_t(LayerHost &L, const int32_t *d_ids, const void *d_loss,
     if (!fused_build_fits(L.catalog, L.tab.fshift, total)) return hipErrorNotSupported;
     const Terms<T> &t = terms_of<T>(L);
     auto kern = &k_fused_build<T, LT, CHECK>;
-    const int lds = (int)(kBuildRange * (sizeof(T) + (sizeof(T) == sizeof(float) ? 4 : 0) + (CHECK ? 4 : 0)));
+    const int lds = (int)(kBuildList * sizeof(uint64_t) +
+                          kBuildRange * (sizeof(T) + (sizeof(T) == sizeof(float) ? 4 : 0) + (CHECK ? 4 : 0)));
     hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(kern), lds);
     if (e != hipSuccess) return e;
     uint32_t *hw = const_cast<uint32_t *>(L.tab.filt) + L.tab.n_fwords;
