@@ -400,9 +400,9 @@ def serving_leg(A, W, torch, n_trials, rates, max_layers=128, n_queries=1000, bu
     del ids
     yet = A.Yet(t_ids, t_off, y.n_trials, y.catalog_size)
     P = A.Pool(yet, pool.ids, pool.losses, "fp64", max_layers=max_layers)
-    min_batch = S.warm_up(yet, P, W.serving_queries(pool, 64, 1e6, stream=999))
+    srv = S.BatchingServer(yet, P)
+    min_batch = srv.warm_up(W.serving_queries(pool, srv.max_batch, 1e6, stream=999))
     log(f"serving leg: record pass wins from {min_batch} layers per group")
-    srv = S.BatchingServer(yet, P, min_batch=min_batch)
     warm = W.serving_queries(pool, 40, 2000.0, stream=998)
     srv.serve(S.make_queries(warm))
     S.serve_one_at_a_time(yet, P, S.make_queries(warm))

@@ -14,12 +14,14 @@ Two servers with the same clock and the same device work per query:
   tables are built on the GPU on a build stream while the previous group runs
   on the run stream.  Whenever the run stream can take more work, everything
   admitted and built so far (up to ARA_MAX_BATCH layers) leaves as one group:
-  one batched pass (dense records for up to 16 layers, sparse records above),
-  or a single-layer pass for a group of one, followed on the same stream by
-  PML/TVaR of the whole group into device memory (the entry point that
-  allocates nothing) and a copy of the results into pinned host memory.  The
+  one batched pass (dense records for up to 16 layers, sparse records above)
+  followed on the same stream by PML/TVaR of the whole group into device
+  memory (the entry point that allocates nothing) and a copy of the results
+  into pinned host memory.  A group smaller than the measured crossover runs
+  as single-layer passes instead, each followed by its own PML/TVaR and copy,
+  so that each of its queries is answered when its own pass is done.  The
   host loop never waits for the device: it keeps admitting and building
-  arrivals and answers a group when its event has fired.
+  arrivals and answers a query when its event has fired.
 * ``serve_one_at_a_time`` -- the baseline: each query in arrival order is
   built, run with the single-layer pass and reduced to PML/TVaR before the
   next one starts.
@@ -78,6 +80,19 @@ def _build(pool: A.Pool, q: Query, stream) -> A.Layer:
     return pool.layer(q.elt_index, q.ret, q.lim, q.occ_ret, q.occ_lim, q.agg_ret, q.agg_lim, stream=stream)
 
 
+@dataclass
+class _InFlight:
+    """A group on the run stream: its queries, YLT buffers, one completion
+    event per query (the same event for every query of a batched pass),
+    the result slot, and how many of its queries have been answered."""
+    group: List[Query]
+    outs: List[torch.Tensor]
+    evs: List[torch.cuda.Event]
+    slot: int
+    per_query: bool
+    next: int = 0
+
+
 def _wait_until(clock, t):
     while True:
         d = t - clock()
@@ -90,8 +105,9 @@ class BatchingServer:
     """Continuous-batching server over one YET and one ELT pool.  Its streams,
     batch objects and result buffers live as long as the server, so repeated
     runs pay no set-up.  A group of fewer than ``min_batch`` queries runs as
-    back-to-back single-layer passes (below the crossover that ``warm_up``
-    measures, a batched pass loses to separate ones)."""
+    single-layer passes, each query answered when its own pass is done
+    (below the crossover that ``warm_up`` measures, a batched pass loses to
+    separate ones)."""
 
     def __init__(self, yet: A.Yet, pool: A.Pool, return_periods=(100.0, 250.0), max_batch: int = L.ARA_MAX_BATCH,
                  min_batch: int = 2):
@@ -112,6 +128,68 @@ class BatchingServer:
                           for _ in range(self.n_slots)]
         self.ylt_bufs = [[] for _ in range(self.n_slots)]
 
+    def warm_up(self, items, sizes=(2, 4, 8, 16, 32, 64)) -> int:
+        """First-use work outside any timed run, and the crossover.
+
+        Every group size from 2 to ``max_batch`` runs once on the first
+        slot's batch, with the layers in arrival order and with the layers
+        of most ELTs (so that both record forms occur), and the largest
+        groups of each form run on every slot: the launch shapes of every
+        layer count are tuned and each slot's device buffers have grown to
+        their largest use before a query is timed.  The crossover -- the
+        smallest group size for which one batched pass beats the
+        single-layer passes of the same layers, measured at ``sizes`` --
+        becomes ``min_batch`` and is returned.  ``items`` must hold at least
+        ``max_batch`` queries."""
+        yet, T = self.yet, self.yet.n_trials
+        qs = make_queries(items)
+        if len(qs) < self.max_batch:
+            raise ValueError("warm-up needs at least max_batch queries")
+        layers = [_build(self.pool, q, None) for q in qs[:self.max_batch]]
+        torch.cuda.synchronize()
+        most = sorted(range(len(layers)), key=lambda i: -len(qs[i].elt_index))
+        outs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in range(self.max_batch)]
+
+        def run(slot, group):
+            if self.batches[slot] is None:
+                self.batches[slot] = A.Batch(yet, group)
+            else:
+                self.batches[slot].rebuild(group)
+            self.batches[slot].run(outs[:len(group)])
+
+        def timed(fn, reps=3):
+            fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / reps
+
+        for n in range(2, self.max_batch + 1):
+            run(0, layers[:n])
+            run(0, [layers[i] for i in most[:n]])
+        for slot in range(self.n_slots):
+            for n in (min(16, self.max_batch), self.max_batch):
+                run(slot, [layers[i] for i in most[:n]])
+        # each layer's own single-layer pass: a group is compared with the
+        # passes of the same layers, whose cost grows with their ELT counts
+        t_single = [timed(lambda l=l: A.run_layer(yet, l, out=outs[0])) for l in layers]
+        t_batch = {n: timed(lambda n=n: run(0, layers[:n])) for n in sizes if n <= self.max_batch}
+        A.pml_tvar_many(outs, self.return_periods)
+        torch.cuda.synchronize()
+        for l in layers:
+            l.close()
+        cross = self.max_batch + 1
+        for n in sorted(t_batch):
+            if t_batch[n] < sum(t_single[:n]):
+                cross = n  # the first measured size that wins
+                break
+        self.min_batch = min(cross, L.ARA_MAX_BATCH)
+        return self.min_batch
+
     def close(self):
         for b in self.batches:
             if b is not None:
@@ -129,7 +207,7 @@ class BatchingServer:
         pending = collections.deque(sorted(queries, key=lambda q: q.arrival))
         waiting: collections.deque = collections.deque()   # arrived, not admitted
         built: List[Query] = []                           # admitted, table being built / ready
-        inflight: collections.deque = collections.deque()  # (queries, outs, event, slot)
+        inflight: collections.deque = collections.deque()  # _InFlight, in launch order
         free_slots = list(range(self.n_slots))
         n_done = 0
         n_launches = 0
@@ -173,9 +251,23 @@ class BatchingServer:
                     while len(bufs) < n:
                         bufs.append(torch.empty(T, dtype=torch.float64, device="cuda"))
                     outs = bufs[:n]
+                r = len(rps)
+                dev, host = self.dev_risk[slot], self.host_risk[slot]
                 if n < max(2, self.min_batch):
-                    for q, o in zip(group, outs):
+                    # below the crossover: single-layer passes, each query
+                    # answered as soon as its own PML/TVaR is on the host
+                    # (query i's [PML, TVaR] at [2 r i, 2 r (i + 1)))
+                    evs = []
+                    for i, (q, o) in enumerate(zip(group, outs)):
                         A.run_layer(yet, q.layer, out=o, stream=run_s)
+                        a = 2 * r * i
+                        A.pml_tvar_many_noalloc([o], rps, dev[a:a + r], dev[a + r:a + 2 * r], stream=run_s)
+                        with torch.cuda.stream(run_s):
+                            host[a:a + 2 * r].copy_(dev[a:a + 2 * r], non_blocking=True)
+                            ev = torch.cuda.Event()
+                            ev.record(run_s)
+                        evs.append(ev)
+                    per_query = True
                 else:
                     layers = [q.layer for q in group]
                     if self.batches[slot] is None:
@@ -183,32 +275,43 @@ class BatchingServer:
                     else:
                         self.batches[slot].rebuild(layers)
                     self.batches[slot].run(outs, stream=run_s)
-                # PML of the group, then its TVaR, in one piece of device
-                # memory: one copy brings both to the host
-                m = n * len(rps)
-                dev, host = self.dev_risk[slot], self.host_risk[slot]
-                A.pml_tvar_many_noalloc(outs, rps, dev[:m], dev[m:2 * m], stream=run_s)
-                with torch.cuda.stream(run_s):
-                    host[:2 * m].copy_(dev[:2 * m], non_blocking=True)
-                    ev = torch.cuda.Event()
-                    ev.record(run_s)
-                inflight.append((group, outs, ev, slot))
-                n_launches += 1
+                    # PML of the group, then its TVaR, in one piece of device
+                    # memory: one copy brings both to the host
+                    m = n * r
+                    A.pml_tvar_many_noalloc(outs, rps, dev[:m], dev[m:2 * m], stream=run_s)
+                    with torch.cuda.stream(run_s):
+                        host[:2 * m].copy_(dev[:2 * m], non_blocking=True)
+                        ev = torch.cuda.Event()
+                        ev.record(run_s)
+                    evs = [ev] * n
+                    per_query = False
+                inflight.append(_InFlight(group, outs, evs, slot, per_query))
+                n_launches += n if per_query else 1
             # completion, in launch order
-            if inflight and inflight[0][2].query():
-                group, outs, ev, slot = inflight.popleft()
+            if inflight and inflight[0].evs[inflight[0].next].query():
+                g = inflight[0]
                 t = clock()
-                n, r = len(group), len(rps)
-                res = self.host_risk[slot][:2 * n * r].numpy().reshape(2, n, r).copy()
-                for i, q in enumerate(group):
+                n, r = len(g.group), len(rps)
+                host = self.host_risk[g.slot]
+                while g.next < n and g.evs[g.next].query():
+                    i = g.next
+                    q = g.group[i]
+                    if g.per_query:
+                        res = host[2 * r * i:2 * r * (i + 1)].numpy().copy()
+                        q.pml, q.tvar = res[:r], res[r:]
+                    else:
+                        q.pml = host[r * i:r * (i + 1)].numpy().copy()
+                        q.tvar = host[n * r + r * i:n * r + r * (i + 1)].numpy().copy()
                     q.done = t
-                    q.batch_size = len(group)
-                    q.pml, q.tvar = res[0, i], res[1, i]
-                    q.ylt = outs[i] if keep_ylt else None
+                    q.batch_size = 1 if g.per_query else n
+                    q.ylt = g.outs[i] if keep_ylt else None
                     q.layer.close()
                     q.layer = None
-                free_slots.append(slot)
-                n_done += len(group)
+                    g.next += 1
+                    n_done += 1
+                if g.next == n:
+                    inflight.popleft()
+                    free_slots.append(g.slot)
                 continue
             if not inflight and not built and not waiting and pending:
                 _wait_until(clock, pending[0].arrival)
@@ -246,55 +349,6 @@ def serve_one_at_a_time(yet: A.Yet, pool: A.Pool, queries: Sequence[Query], retu
         q.ylt = out if keep_ylt else None
         lay.close()
     return _summary(queries, len(queries))
-
-
-def warm_up(yet: A.Yet, pool: A.Pool, items, sizes=(2, 4, 8, 16, 32, 64)) -> int:
-    """First-use work outside any timed run (the batch launch shape of every
-    power-of-two batch size, tuned once per process; allocator growth), and
-    the crossover: the smallest group for which one record pass beats the
-    same number of single-layer passes.  Returns that group size."""
-    qs = make_queries(items[:max(sizes)])
-    layers = [_build(pool, q, None) for q in qs]
-    torch.cuda.synchronize()
-    T = yet.n_trials
-
-    def timed(fn, reps=3):
-        fn()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
-
-    one = torch.empty(T, dtype=torch.float64, device="cuda")
-    t_single = timed(lambda: A.run_layer(yet, layers[0], out=one))
-    b = None
-    t_batch = {}
-    for n in sizes:
-        if n > len(layers):
-            break
-        outs = [torch.empty(T, dtype=torch.float64, device="cuda") for _ in range(n)]
-        if b is None:
-            b = A.Batch(yet, layers[:n])
-        else:
-            b.rebuild(layers[:n])
-        t_batch[n] = timed(lambda: b.run(outs))
-        A.pml_tvar_many(outs, (100.0, 250.0))
-    torch.cuda.synchronize()
-    if b is not None:
-        b.close()
-    for l in layers:
-        l.close()
-    cross = max(sizes) + 1
-    for n in sorted(t_batch):
-        if t_batch[n] < n * t_single:
-            # first measured size that wins; interpolate down to the exact crossover
-            cross = max(2, min(n, int(np.ceil(t_batch[n] / t_single))))
-            break
-    return min(cross, L.ARA_MAX_BATCH)
 
 
 def _pct(x: np.ndarray, p: float) -> float:

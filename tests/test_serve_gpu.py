@@ -115,6 +115,33 @@ def test_served_answers_same_alone_and_in_mix(prec, max_layers):
         assert_risk_close(q.pml, q.tvar, rp, rt, prec, ref)
 
 
+def test_warmed_server_answers_same_alone_and_in_mix():
+    """A server whose warm-up ran every group size (growing its batches'
+    buffers, tuning their launch shapes) and chose its crossover still
+    answers each query as the one-at-a-time server does."""
+    ids, off, pool = _setup()
+    T, C = len(off) - 1, 30000
+    yet = A.yet_from_numpy(ids, off, T, C)
+    P = A.Pool(yet, pool.ids, pool.losses, "fp64", max_layers=24)
+    srv = S.BatchingServer(yet, P, RPS, max_batch=8)
+    warm = _queries(pool, 8, 1e6, seed=5)
+    mb = srv.warm_up(warm, sizes=(2, 4, 8))
+    assert mb == srv.min_batch and 2 <= mb <= 9
+    assert P.free_slots == 24
+    items = _queries(pool, 60, 3000.0, seed=6)
+    qs = S.make_queries(items)
+    srv.serve(qs, keep_ylt=True)
+    torch.cuda.synchronize()
+    srv.close()
+    alone = S.make_queries(items)
+    S.serve_one_at_a_time(yet, P, alone, RPS, keep_ylt=True)
+    torch.cuda.synchronize()
+    for q, a in zip(qs, alone):
+        assert torch.equal(q.ylt, a.ylt), q.qid
+        assert np.array_equal(q.pml, a.pml) and np.array_equal(q.tvar, a.tvar)
+    assert P.free_slots == 24
+
+
 def test_pml_tvar_many_matches_single():
     rng = np.random.default_rng(0)
     ys = [torch.from_numpy(rng.lognormal(5, 2, 5000) * (rng.uniform(size=5000) < 0.5)).cuda() for _ in range(20)]
