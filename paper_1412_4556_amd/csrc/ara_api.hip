@@ -352,9 +352,7 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
         const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
         if (ara::fused_build_fits(C, fshift, (int64_t)n)) {
             // one launch builds the table from the ELTs as given (binary64
-            // losses) and checks every entry on the way (the IDs' part is
-            // 256-byte aligned and rounded up to 256 bytes: the build reads
-            // whole 16-byte granules)
+            // losses) and checks every entry on the way
             const size_t b_ids = up(n * sizeof(int32_t)), b_loss = up(n * sizeof(double));
             const size_t need = b_ids + b_loss + 256;
             Staging &sg = staging_for(dev);
@@ -703,10 +701,7 @@ ara_status ara_create_pool(ara_yet yet, int32_t n_elts, const int32_t *h_elt_ids
     filter_geometry(yet->catalog, p->fshift, p->n_fwords, p->n_hwords, p->hshift);
     const size_t total = (size_t)start[n_elts];
     hipStream_t s = ara::internal_stream();
-    // padded to a multiple of four IDs: the table build reads whole 16-byte
-    // granules, up to the granule of an ELT's last entry
-    const size_t ids_alloc = (total + 3) / 4 * 4;
-    hipError_t e = dev_alloc(&p->d_ids, (ids_alloc > 0 ? ids_alloc : 4) * sizeof(int32_t));
+    hipError_t e = dev_alloc(&p->d_ids, total * sizeof(int32_t));
     if (e == hipSuccess && total)
         e = hipMemcpyAsync(p->d_ids, h_elt_ids, total * sizeof(int32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

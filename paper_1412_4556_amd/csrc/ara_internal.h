@@ -200,8 +200,9 @@ size_t batch_lds_bytes(int32_t n_layers, int threads);
 // binary32 scratch [catalog] for FP32C, else unused.
 hipError_t launch_pool_layer(LayerHost &L, const int32_t *d_ids, const void *d_loss, const int64_t *h_off,
                              const int32_t *h_idx, int32_t n, float *d_lo, hipStream_t s);
-// The same table in one launch (plus one clearing the hashed filter) when
-// fused_build_fits: one work-group per kBuildRange catalogue events.
+// The same table in three launches when fused_build_fits: the filter words
+// cleared, each range's entries listed (one read of every ID), and the table
+// with one work-group per kBuildRange catalogue events.
 // host_losses: d_loss holds the ELTs' binary64 losses as given by the host,
 // and the kernel validates every entry into *d_flags (bit 1 ID out of range,
 // 2 duplicate ID in one ELT, 4 bad loss; cleared by the caller); else
@@ -210,11 +211,12 @@ hipError_t launch_pool_layer(LayerHost &L, const int32_t *d_ids, const void *d_l
 constexpr int kBuildRange = 8192;
 constexpr int kBuildThreads = 1024;
 constexpr int kBuildUnroll = 16;
-// Entries of a range the build lists in LDS before adding them (a range
-// with more takes the ELTs one at a time); a multiple of kBuildThreads, and
-// with the sums it stays within the 160 KiB of LDS.
+// Entries of a range the build lists before adding them (a range with more
+// reads every ID of the layer instead, taking the ELTs one at a time); a
+// multiple of kBuildThreads.
 constexpr int kBuildList = 4 * kBuildThreads;
-constexpr int64_t kBuildReadBudget = (int64_t)1 << 30;  // IDs read over all work-groups
+// IDs read over all work-groups if every range overflowed its list
+constexpr int64_t kBuildReadBudget = (int64_t)1 << 30;
 struct BuildSegs {
     int64_t begin[kMaxElts];  // ELT j of the layer: entries begin[j] .. begin[j] + count[j]
     int64_t count[kMaxElts];

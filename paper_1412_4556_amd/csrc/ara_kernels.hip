@@ -1695,68 +1695,118 @@ __device__ __forceinline__ void build_chunk_ids(const int32_t *__restrict__ ids,
     }
 }
 
-// The scan of a layer's ELTs reads 16-byte granules: ELT j's entries are
-// positions lead_j .. lead_j + m_j - 1 of its granule-aligned span starting
-// at begin_j rounded down to a multiple of four (lead_j = begin_j mod 4).  A
-// chunk is kBuildGranules granules per thread (thread t takes granules
-// c0 / 4 + q B + t); granules past the ELT's last one read that one (the ID
-// arrays are padded to a multiple of four entries and 16-byte aligned).
-constexpr int kBuildGranules = 2;
-struct BuildCursor {
-    int j;       // ELT (sg.n: done)
-    int64_t c0;  // chunk start within the ELT's span (a multiple of 4)
-};
-
-__device__ __forceinline__ int64_t build_span(const BuildSegs &sg, int j) {
-    return (sg.begin[j] & 3) + sg.count[j];
+// Where the build keeps a range's entry list until it adds them: range g
+// (catalogue events [g R, g R + n_g), R = kBuildRange) lists its entries in
+// its own part of the table, occ[g R ..], which is written only once the list
+// has been read, and counts them in the first block-filter word of the range,
+// written only by the range's own work-group once it has read the count.
+template <typename T>
+__device__ __forceinline__ uint64_t *range_list(T *occ, int64_t g) {
+    return reinterpret_cast<uint64_t *>(occ + g * kBuildRange);
 }
 
-__device__ __forceinline__ void build_first_elt(const BuildSegs &sg, BuildCursor &cc) {
-    while (cc.j < sg.n && sg.count[cc.j] == 0) ++cc.j;
+template <typename T>
+__device__ __forceinline__ int range_capacity(int64_t g, int32_t catalog) {
+    const int64_t left = (int64_t)catalog + 1 - g * kBuildRange;
+    const int64_t n = left < kBuildRange ? left : kBuildRange;
+    const int64_t cap = n * (int64_t)sizeof(T) / (int64_t)sizeof(uint64_t);
+    return cap < kBuildList ? (int)cap : kBuildList;
 }
 
-__device__ __forceinline__ void build_next(const BuildSegs &sg, BuildCursor &cc) {
-    cc.c0 += 4LL * kBuildGranules * blockDim.x;
-    if (cc.c0 >= build_span(sg, cc.j)) {
-        cc.c0 = 0;
-        ++cc.j;
-        build_first_elt(sg, cc);
+// The entry lists of a layer's ranges: one work-group per kListChunk entries
+// of one ELT (blockIdx.y), each entry read once.  An entry goes to the list
+// of its event's range, at a place taken from the range's count: the
+// work-group first counts its entries per range in LDS and reserves each
+// range's share with one atomic add on its count (one atomic per entry
+// where the ranges outnumber kListHist).  The order of a list is
+// arbitrary; the adds that read it keep the layer order.  Entries past a
+// range's capacity are counted but not written (that range then reads the
+// ELTs again).  The counts start at zero (the filter words are cleared
+// beforehand).  CHECK: an ID outside [0, catalog) sets bit 1 of *flags.
+constexpr int kListThreads = 256;
+constexpr int kListPerThread = 8;
+constexpr int kListChunk = kListThreads * kListPerThread;
+constexpr int kListHist = 4096;
+template <typename T, bool CHECK>
+__global__ __launch_bounds__(kListThreads) void k_build_lists(const int32_t *__restrict__ ids, BuildSegs sg,
+                                                              int32_t catalog, T *__restrict__ occ,
+                                                              uint32_t *__restrict__ filt, int32_t range_words,
+                                                              int *flags) {
+    static_assert(kBuildRange == (1 << 13), "an event's range is its ID >> 13");
+    __shared__ int hist[kListHist];
+    const int j = blockIdx.y;
+    const int64_t m = sg.count[j];
+    const int64_t i0 = (int64_t)blockIdx.x * kListChunk;
+    if (i0 >= m) return;  // uniform: the work-group has no entries
+    const int n_ranges = (int)(((int64_t)catalog + kBuildRange) >> 13);
+    const bool local = n_ranges <= kListHist;
+    if (local) {
+        for (int k = threadIdx.x; k < n_ranges; k += blockDim.x) hist[k] = 0;
+        __syncthreads();
     }
-}
-
-__device__ __forceinline__ void build_granules(const int32_t *__restrict__ ids, const BuildSegs &sg,
-                                               const BuildCursor &cc, int32_t (&e)[4 * kBuildGranules]) {
-    const int64_t b0 = sg.begin[cc.j] & ~3LL;
-    const int32_t *__restrict__ seg = ids + b0 + cc.c0;  // uniform, 16-byte aligned
-    const uint32_t last = (uint32_t)((build_span(sg, cc.j) - 1 - cc.c0) >> 2);
+    const int32_t *__restrict__ seg = ids + sg.begin[j] + i0;
+    const uint32_t n_here = (uint32_t)(m - i0 < kListChunk ? m - i0 : kListChunk);
+    int32_t e[kListPerThread];
 #pragma unroll
-    for (int q = 0; q < kBuildGranules; ++q) {
-        const uint32_t g = (uint32_t)(q * blockDim.x + threadIdx.x);
-        const int4 v = *reinterpret_cast<const int4 *>(seg + 4 * (g < last ? g : last));
-        e[4 * q] = v.x;
-        e[4 * q + 1] = v.y;
-        e[4 * q + 2] = v.z;
-        e[4 * q + 3] = v.w;
+    for (int u = 0; u < kListPerThread; ++u) {
+        const uint32_t i = (uint32_t)(u * kListThreads + threadIdx.x);
+        e[u] = seg[i < n_here ? i : n_here - 1];
     }
+    int bad = 0;
+    int place[kListPerThread];
+#pragma unroll
+    for (int u = 0; u < kListPerThread; ++u) {
+        const uint32_t i = (uint32_t)(u * kListThreads + threadIdx.x);
+        place[u] = -1;
+        if (i >= n_here) continue;
+        if ((uint32_t)e[u] >= (uint32_t)catalog) {
+            if (CHECK) bad |= 1;
+            e[u] = -1;
+            continue;
+        }
+        const int g = e[u] >> 13;
+        place[u] = local ? atomicAdd(&hist[g], 1) : atomicAdd(&filt[(int64_t)g * range_words], 1u);
+    }
+    if (local) {
+        __syncthreads();
+        // each range's share of the list, from its count
+        for (int k = threadIdx.x; k < n_ranges; k += blockDim.x) {
+            const int c = hist[k];
+            if (c) hist[k] = (int)atomicAdd(&filt[(int64_t)k * range_words], (uint32_t)c);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < kListPerThread; ++u) {
+        if (place[u] < 0) continue;
+        const int g = e[u] >> 13;
+        const int at = place[u] + (local ? hist[g] : 0);
+        if (at < range_capacity<T>(g, catalog)) {
+            const uint32_t off = (uint32_t)e[u] & (kBuildRange - 1);
+            const int64_t pos = sg.begin[j] + i0 + u * kListThreads + threadIdx.x;
+            range_list(occ, g)[at] = ((uint64_t)j << 53) | ((uint64_t)off << 40) | (uint64_t)pos;
+        }
+    }
+    if (CHECK && bad) atomicOr(flags, bad);
 }
 
-// A layer's fused table in one launch.  Work-group g owns the catalogue
-// events [g R, (g + 1) R) (R = kBuildRange) and keeps their sums in LDS.  It
-// reads the IDs of every ELT of the layer (the next chunk's loads in flight
-// while a chunk is checked) and lists the entries of its own events in LDS;
-// it then loads their losses together and adds FT1 of them to the sums one
-// ELT after the other (an ELT holds an event at most once, so no two
-// threads of one ELT add to the same slot; a barrier separates the ELTs),
-// which is the order of k_pool_add.  A range holding more than kBuildList
-// entries takes the ELTs one at a time instead, reading each entry's loss
-// as it goes.  It then applies the occurrence terms, writes its range of
-// the table and its words of the block filter (a range covers whole filter
-// words) and sets the hashed filter's bits of its non-zero events (words
-// cleared beforehand).  Bitwise the table of k_pool_zero / k_pool_add /
-// k_pool_finish and the filter kernels.
-// CHECK (ELTs from the host): also validates every entry and reports in
-// *flags: 1 an ID outside [0, catalog), 2 an ID twice in one ELT, 4 a loss
-// that is negative, infinite or NaN (the table is then not used).
+// A layer's fused table from the entry lists of k_build_lists.  Work-group
+// g owns the catalogue events [g R, (g + 1) R) (R = kBuildRange) and keeps
+// their sums in LDS.  It reads its range's count and list, loads the listed
+// losses together and adds FT1 of them to the sums one ELT after the other
+// (an ELT holds an event at most once, so no two threads of one ELT add to
+// the same slot; a barrier separates the ELTs), which is the order of
+// k_pool_add.  A range whose list overflowed its capacity takes the ELTs one
+// at a time instead, reading each ELT's IDs and losses as it goes.  It then
+// applies the occurrence terms, writes its range of the table and its words
+// of the block filter (a range covers whole filter words) and sets the
+// hashed filter's bits of its non-zero events (words cleared beforehand).
+// Bitwise the table of k_pool_zero / k_pool_add / k_pool_finish and the
+// filter kernels.
+// CHECK (ELTs from the host): also validates every loss and every pair of
+// entries of one event in one ELT, reporting in *flags: 2 an ID twice in one
+// ELT, 4 a loss that is negative, infinite or NaN (the table is then not
+// used; k_build_lists reports IDs out of range).
 // LT: type of the stored losses (binary64 from the host; the pool's own
 // type for pool layers); the conversion to T is the one the host would do.
 // A list entry: bits 0..39 the entry's position in the arrays, 40..52 its
@@ -1772,76 +1822,43 @@ __global__ __launch_bounds__(kBuildThreads) void k_fused_build(const int32_t *__
     static_assert(kBuildRange <= (1 << 13) && kMaxElts <= 32, "list entry fields");
     constexpr int kPerThread = kBuildList / kBuildThreads;
     extern __shared__ uint64_t build_lds[];
-    __shared__ int list_n;
-    uint64_t *list = build_lds;  // [kBuildList]
-    T *hi = reinterpret_cast<T *>(list + kBuildList);
+    T *hi = reinterpret_cast<T *>(build_lds);
     float *lo = reinterpret_cast<float *>(hi + kBuildRange);  // FP32C: compensation terms
     int *stamp = reinterpret_cast<int *>(lo + (sizeof(T) == sizeof(float) ? kBuildRange : 0));  // CHECK
-    const int64_t base = (int64_t)blockIdx.x * kBuildRange;
+    const int64_t g = blockIdx.x;
+    const int64_t base = g * kBuildRange;
     const int64_t top = base + kBuildRange < (int64_t)catalog + 1 ? base + kBuildRange : (int64_t)catalog + 1;
     const uint32_t nloc = (uint32_t)(top - base);
+    const int wshift = 5 + fshift;
+    const int64_t w0 = base >> wshift;
+    // the count (a range past the last filter word holds only the zero slot)
+    const int n_list = w0 < n_fwords ? (int)filt[w0] : 0;
+    const bool listed = n_list <= range_capacity<T>(g, catalog);
+    uint64_t le[kPerThread];
+    LT lv[kPerThread];
+    if (listed) {
+        // the listed entries and their losses, all loads in flight together
+        const uint64_t *__restrict__ list = range_list(occ, g);
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const int sl = threadIdx.x + k * blockDim.x;
+            le[k] = sl < n_list ? list[sl] : ~0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            lv[k] = LT(0);
+            if (le[k] != ~0ull) lv[k] = loss[(int64_t)(le[k] & ((1ull << 40) - 1))];
+        }
+    }
     for (int k = threadIdx.x; k < kBuildRange; k += blockDim.x) {
         hi[k] = T(0);
         if (sizeof(T) == sizeof(float)) lo[k] = 0.0f;
         if (CHECK) stamp[k] = -1;
     }
-    if (threadIdx.x == 0) list_n = 0;
     __syncthreads();
     int bad = 0;
-    // the entries of this range, in any order (the next chunk's granules in
-    // flight while one is checked)
-    // (IDs are in [0, catalog) after the check, so e - base fits 32 bits)
-    const uint32_t base32 = (uint32_t)base;
-    auto scan = [&](const BuildCursor &cc, const int32_t(&e)[4 * kBuildGranules]) {
-        const int64_t b0 = sg.begin[cc.j] & ~3LL;
-        const uint32_t lead = (uint32_t)(sg.begin[cc.j] & 3);
-        const int64_t span = build_span(sg, cc.j) - cc.c0;  // positions of the ELT from the chunk's start on
-#pragma unroll
-        for (int q = 0; q < kBuildGranules; ++q)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const uint32_t r = 4u * (q * blockDim.x + threadIdx.x) + v;  // position in the chunk
-                const int32_t id = e[4 * q + v];
-                if ((int64_t)r >= span || (cc.c0 == 0 && r < lead)) continue;
-                if (CHECK && (id < 0 || id >= catalog)) {
-                    bad |= 1;
-                    continue;
-                }
-                const uint32_t off = (uint32_t)id - base32;
-                if (off >= nloc) continue;
-                const int slot = atomicAdd(&list_n, 1);
-                if (slot < kBuildList)
-                    list[slot] = ((uint64_t)cc.j << 53) | ((uint64_t)off << 40) | (uint64_t)(b0 + cc.c0 + r);
-            }
-    };
-    BuildCursor ca{0, 0};
-    build_first_elt(sg, ca);
-    int32_t ea[4 * kBuildGranules], eb[4 * kBuildGranules];
-    if (ca.j < sg.n) build_granules(ids, sg, ca, ea);
-    while (ca.j < sg.n) {
-        BuildCursor cb = ca;
-        build_next(sg, cb);
-        if (cb.j < sg.n) build_granules(ids, sg, cb, eb);
-        scan(ca, ea);
-        if (cb.j >= sg.n) break;
-        ca = cb;
-        build_next(sg, ca);
-        if (ca.j < sg.n) build_granules(ids, sg, ca, ea);
-        scan(cb, eb);
-    }
-    __syncthreads();
-    const int n_list = list_n;
-    if (n_list <= kBuildList) {
-        // their losses together, then the sums in layer order
-        uint64_t le[kPerThread];
-        LT lv[kPerThread];
-#pragma unroll
-        for (int k = 0; k < kPerThread; ++k) {
-            const int sl = threadIdx.x + k * blockDim.x;
-            le[k] = sl < n_list ? list[sl] : ~0ull;
-            lv[k] = LT(0);
-            if (sl < n_list) lv[k] = loss[(int64_t)(le[k] & ((1ull << 40) - 1))];
-        }
+    if (listed) {
+        // the sums in layer order
         for (int jj = 0; jj < sg.n; ++jj) {
             const T r = (T)sg.ret[jj], u = (T)sg.lim[jj];
 #pragma unroll
@@ -1851,7 +1868,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_fused_build(const int32_t *__
             __syncthreads();
         }
     } else {
-        // a crowded range: one ELT at a time
+        // an overflowed range: one ELT at a time
         for (int jj = 0; jj < sg.n; ++jj) {
             const int64_t b = sg.begin[jj], m = sg.count[jj];
             const T r = (T)sg.ret[jj], u = (T)sg.lim[jj];
@@ -1861,7 +1878,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_fused_build(const int32_t *__
 #pragma unroll 4
                 for (int q = 0; q < kBuildUnroll; ++q) {
                     const int64_t i = ic + (int64_t)q * blockDim.x + threadIdx.x;
-                    if (i >= m || e[q] < 0 || e[q] >= catalog) continue;  // range errors flagged above
+                    if (i >= m || e[q] < 0 || e[q] >= catalog) continue;  // range errors flagged by the lists
                     const uint32_t off = (uint32_t)((int64_t)e[q] - base);
                     if (off >= nloc) continue;
                     build_add<T, LT, CHECK>(hi, lo, stamp, off, loss[b + i], jj, r, u, bad);
@@ -1884,8 +1901,6 @@ __global__ __launch_bounds__(kBuildThreads) void k_fused_build(const int32_t *__
     // events 2^(fshift + 5) w + 32 t + b (t < 2^fshift) has a non-zero
     // occurrence loss (the range starts on a word: kBuildRange is a multiple
     // of 2^(fshift + 5), and holds the zero slot's slot as 0)
-    const int wshift = 5 + fshift;
-    const int64_t w0 = base >> wshift;
     const int n_w = kBuildRange >> wshift;
     for (int q = threadIdx.x; q < n_w; q += blockDim.x) {
         const int64_t w = w0 + q;
@@ -2208,7 +2223,7 @@ const Terms<float> &terms_of<float>(const LayerHost &L) {
 bool fused_build_fits(int64_t catalog, int32_t fshift, int64_t n_entries) {
     if ((kBuildRange >> (5 + fshift)) < 1 || ((kBuildRange >> (5 + fshift)) << (5 + fshift)) != kBuildRange) return false;
     const int64_t groups = (catalog + 1 + kBuildRange - 1) / kBuildRange;
-    // every work-group reads every ID of the layer
+    // a work-group whose range overflows its list reads every ID of the layer
     return groups * (n_entries > 0 ? n_entries : 1) <= kBuildReadBudget;
 }
 
@@ -2229,18 +2244,24 @@ hipError_t fused_build_t(LayerHost &L, const int32_t *d_ids, const void *d_loss,
     if (!fused_build_fits(L.catalog, L.tab.fshift, total)) return hipErrorNotSupported;
     const Terms<T> &t = terms_of<T>(L);
     auto kern = &k_fused_build<T, LT, CHECK>;
-    const int lds = (int)(kBuildList * sizeof(uint64_t) +
-                          kBuildRange * (sizeof(T) + (sizeof(T) == sizeof(float) ? 4 : 0) + (CHECK ? 4 : 0)));
+    const int lds = (int)(kBuildRange * (sizeof(T) + (sizeof(T) == sizeof(float) ? 4 : 0) + (CHECK ? 4 : 0)));
     hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(kern), lds);
     if (e != hipSuccess) return e;
-    uint32_t *hw = const_cast<uint32_t *>(L.tab.filt) + L.tab.n_fwords;
-    if (L.tab.n_hwords > 0)
-        hipLaunchKernelGGL((k_fill_zero<uint32_t>), dim3(64), dim3(256), 0, s, hw, (int64_t)L.tab.n_hwords);
+    T *occ = static_cast<T *>(const_cast<void *>(L.tab.occ));
+    uint32_t *filt = const_cast<uint32_t *>(L.tab.filt);
+    // the filter words hold the ranges' counts until the build writes them
+    hipLaunchKernelGGL((k_fill_zero<uint32_t>), dim3(64), dim3(256), 0, s, filt,
+                       (int64_t)(L.tab.n_fwords + L.tab.n_hwords));
+    int64_t longest = 0;
+    for (int j = 0; j < n; ++j) longest = sg.count[j] > longest ? sg.count[j] : longest;
+    const int range_words = kBuildRange >> (5 + L.tab.fshift);
+    if (longest > 0)
+        hipLaunchKernelGGL((k_build_lists<T, CHECK>), dim3((unsigned)((longest + kListChunk - 1) / kListChunk), (unsigned)n),
+                           dim3(kListThreads), 0, s, d_ids, sg, L.catalog, occ, filt, range_words, d_flags);
     const int64_t groups = ((int64_t)L.catalog + 1 + kBuildRange - 1) / kBuildRange;
     hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kBuildThreads), lds, s, d_ids, static_cast<const LT *>(d_loss),
-                       sg, L.catalog, t.occ_ret, t.occ_lim, static_cast<T *>(const_cast<void *>(L.tab.occ)),
-                       const_cast<uint32_t *>(L.tab.filt), L.tab.n_fwords, L.tab.fshift, hw, L.tab.n_hwords,
-                       L.tab.hshift, d_flags);
+                       sg, L.catalog, t.occ_ret, t.occ_lim, occ, filt, L.tab.n_fwords, L.tab.fshift,
+                       filt + L.tab.n_fwords, L.tab.n_hwords, L.tab.hshift, d_flags);
     return hipGetLastError();
 }
 }  // namespace

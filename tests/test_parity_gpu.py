@@ -522,6 +522,11 @@ def test_fused_build_concentrated_elts(prec):
     yc = A.run_layer(yet, A.Layer(yet, spec, prec, "compact")).cpu().numpy()
     assert np.array_equal(yf, yc)
     assert (yf > 0).mean() > 0.05
+    # the same table built from a device pool of the ELTs
+    P = A.Pool(yet, eids, elos, prec, max_layers=1)
+    lp = P.layer(np.arange(J, dtype=np.int32), ret, lim, 500.0, 1e6, 1e4, 1e8)
+    assert np.array_equal(A.run_layer(yet, lp).cpu().numpy(), yf)
+    lp.close()
     ref = oracle_run(ids, None, T, C, 200, spec)
     assert_close_to_oracle(yf, ref, prec)
     bad_ids = [a.copy() for a in eids]
@@ -534,3 +539,44 @@ def test_fused_build_concentrated_elts(prec):
     with pytest.raises(L.AraError) as ei:
         A.Layer(yet, W.LayerSpec(eids, bad_los, ret, lim, 500.0, 1e6, 1e4, 1e8), prec, "fused")
     assert ei.value.name == "ARA_ERR_VALUE"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_fused_build_more_ranges_than_list_counters(prec):
+    """A catalogue of 40M events: 4,883 ranges of 8,192 events, more than
+    the build's per-work-group range counters, so every entry reserves its
+    place in its range's list with an atomic of its own.  The table is
+    bitwise the compact layout's (from the host and from a device pool),
+    the oracle's within tolerance, and a duplicate ID is still found."""
+    C = 40_000_000
+    rng = np.random.default_rng(2029)
+    eids = [rng.choice(C, size=3000, replace=False).astype(np.int32) for _ in range(4)]
+    # 500 events in two ELTs of the layer (ELT 2 keeps 3,000 distinct IDs)
+    eids[2] = np.concatenate([eids[1][:500], rng.permutation(np.setdiff1d(eids[2], eids[1][:500]))[:2500]])
+    assert all(len(np.unique(e)) == 3000 for e in eids)
+    elos = [rng.lognormal(8.0, 2.0, 3000) for _ in range(4)]
+    ret = np.array([np.quantile(l, 0.1) for l in elos])
+    lim = np.array([np.quantile(l, 0.9) for l in elos])
+    spec = W.LayerSpec(eids, elos, ret, lim, 500.0, 1e6, 1e4, 1e8)
+    T = 500
+    lens = rng.poisson(60, T)
+    off = np.zeros(T + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    pool = np.concatenate(eids)
+    ids = np.where(rng.random(off[-1]) < 0.6, rng.choice(pool, off[-1]), rng.integers(0, C, off[-1])).astype(np.int32)
+    yet = A.yet_from_numpy(ids, off, T, C)
+    yf = A.run_layer(yet, A.Layer(yet, spec, prec, "fused")).cpu().numpy()
+    yc = A.run_layer(yet, A.Layer(yet, spec, prec, "compact")).cpu().numpy()
+    assert np.array_equal(yf, yc)
+    assert (yf > 0).mean() > 0.1
+    P = A.Pool(yet, eids, elos, prec, max_layers=1)
+    lp = P.layer(np.arange(4, dtype=np.int32), ret, lim, 500.0, 1e6, 1e4, 1e8)
+    assert np.array_equal(A.run_layer(yet, lp).cpu().numpy(), yf)
+    lp.close()
+    ref = oracle_run(ids, off, T, C, 0, spec)
+    assert_close_to_oracle(yf, ref, prec)
+    bad_ids = [a.copy() for a in eids]
+    bad_ids[0][2999] = bad_ids[0][0]
+    with pytest.raises(L.AraError) as ei:
+        A.Layer(yet, W.LayerSpec(bad_ids, elos, ret, lim, 500.0, 1e6, 1e4, 1e8), prec, "fused")
+    assert ei.value.name == "ARA_ERR_DUP_EVENT"
