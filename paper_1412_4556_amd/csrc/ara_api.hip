@@ -351,7 +351,7 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
         h.tab.hshift = hshift;
         const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
         if (ara::fused_build_fits(C, fshift, (int64_t)n)) {
-            // one launch builds the table from the ELTs as given (binary64
+            // the GPU build makes the table from the ELTs as given (binary64
             // losses) and checks every entry on the way
             const size_t b_ids = up(n * sizeof(int32_t)), b_loss = up(n * sizeof(double));
             const size_t need = b_ids + b_loss + 256;
@@ -551,8 +551,8 @@ ara_status ara_create_layer(ara_yet yet, int32_t n_elts, const int32_t *h_elt_id
     std::vector<int64_t> start;
     ara_status vst = elt_starts(C, n_elts, h_elt_ids, h_elt_losses, h_elt_sizes, start);
     if (vst != ARA_OK) return vst;
-    // a fused layer built in one launch has its entries checked by that
-    // launch; every other layer checks them here
+    // a fused layer built on the GPU has its entries checked by the build's
+    // kernels; every other layer checks them here
     int32_t fshift = 0, n_fwords = 0, n_hwords = 0, hshift = 0;
     filter_geometry(C, fshift, n_fwords, n_hwords, hshift);
     const bool fused = layout == ARA_LAYOUT_AUTO || layout == ARA_LAYOUT_FUSED;
