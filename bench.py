@@ -110,17 +110,28 @@ def time_layer(A, torch, yet, lay, ylt, steps, warmup, rps, with_pml=True):
     return (t1 - t0) * 1e3 / steps, sum(k_ms) / len(k_ms), min(k_ms), res
 
 
-def time_step(A, torch, yet, pool, spec, ylt, steps, warmup, rps):
+def time_step(A, torch, yet, pool, spec, ylt, steps, warmup, rps, pipelined=True):
     """The headline step (fused table from the device-resident ELTs, trial
     pass, PML/TVaR to the host).  Returns the wall time per step, the mean
     build and pass times (HIP events on the launch stream), the fastest pass
-    and the last step's PML/TVaR."""
+    and the last step's PML/TVaR.
+
+    pipelined: step i + 1 is queued before step i's PML/TVaR is read on the
+    host (PML/TVaR into device memory with the entry point that allocates
+    nothing, an asynchronous copy into pinned host memory and an event per
+    step; two table slots of the pool alternate), so the GPU does not wait
+    for the host between steps.  Otherwise every step ends with the
+    synchronous ara_pml_tvar before the next one is issued."""
     import numpy as np
 
     stream = torch.cuda.current_stream()
     idx = np.arange(spec.n_elts, dtype=np.int32)
+    r = len(rps)
+    dev = torch.empty(2 * r, dtype=torch.float64, device="cuda")
+    host = [torch.empty(2 * r, dtype=torch.float64, pin_memory=True) for _ in range(2)]
+    done = [torch.cuda.Event() for _ in range(2)]
 
-    def one(ev=None):
+    def launch(i, ev=None):
         if ev:
             ev[0].record(stream)
         lay = pool.layer(idx, spec.ret, spec.lim, spec.occ_ret, spec.occ_lim, spec.agg_ret, spec.agg_lim,
@@ -130,18 +141,42 @@ def time_step(A, torch, yet, pool, spec, ylt, steps, warmup, rps):
         A.run_layer(yet, lay, out=ylt, stream=stream)
         if ev:
             ev[2].record(stream)
-        res = A.pml_tvar(ylt, rps, stream=stream)
-        lay.close()  # the slot's next build is queued behind this pass on the same stream
+        if not pipelined:
+            res = A.pml_tvar(ylt, rps, stream=stream)
+            lay.close()  # the slot's next build is queued behind this pass on the same stream
+            return res
+        A.pml_tvar_many_noalloc([ylt], rps, dev[:r], dev[r:], stream=stream)
+        with torch.cuda.stream(stream):
+            host[i % 2].copy_(dev, non_blocking=True)
+        done[i % 2].record(stream)
+        return (i, lay)
+
+    def finish(p):
+        i, lay = p
+        done[i % 2].synchronize()
+        out = host[i % 2].numpy().copy()
+        lay.close()
+        return out[:r], out[r:]
+
+    def run(n, evs=None):
+        res, prev = None, None
+        for i in range(n):
+            p = launch(i, evs[i] if evs else None)
+            if not pipelined:
+                res = p
+                continue
+            if prev is not None:
+                res = finish(prev)
+            prev = p
+        if prev is not None:
+            res = finish(prev)
         return res
 
-    for _ in range(warmup):
-        one()
+    run(warmup)
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     t0 = time.perf_counter()
-    res = None
-    for i in range(steps):
-        res = one(evs[i])
+    res = run(steps, evs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     b_ms = [e[0].elapsed_time(e[1]) for e in evs]
@@ -501,6 +536,11 @@ def main():
     pool = A.Pool(yet, spec.elt_ids, spec.elt_losses, args.precision, max_layers=2)
     ms_step, b_ms, k_ms, k_min, (pml, tvar) = time_step(A, torch, yet, pool, spec, ylt, args.steps, args.warmup,
                                                         rps)
+    # the same steps one at a time (each waits for its PML/TVaR before the
+    # next is issued): the latency of one step, with the host's turnaround
+    ms_sync, _, _, _, (pml_s, tvar_s) = time_step(A, torch, yet, pool, spec, ylt, args.steps, args.warmup, rps,
+                                                  pipelined=False)
+    assert np.array_equal(pml_s, pml) and np.array_equal(tvar_s, tvar), "pipelined and synchronous steps differ"
     ylt_host = ylt.cpu().numpy()  # the timed steps' YLT, for the parity check against the oracle
     # the same layer built from host ELTs (upload over PCIe, checks, table),
     # outside the step; the second build is the steady-state cost
@@ -513,7 +553,8 @@ def main():
     log(f"layer: {J} ELTs, layout {lay.layout}, precision {lay.precision}, {lay.device_bytes} device bytes")
     algo_bytes = T * K * 4 + T * 8 + lay.device_bytes
     achieved = algo_bytes / (k_ms * 1e-3) / 1e9
-    log(f"step {ms_step:.3f} ms (table build {b_ms:.3f} ms, trial pass {k_ms:.3f} ms, min {k_min:.3f}), "
+    log(f"step {ms_step:.3f} ms pipelined, {ms_sync:.3f} ms one at a time (table build {b_ms:.3f} ms, "
+        f"trial pass {k_ms:.3f} ms, min {k_min:.3f}), "
         f"{achieved:.0f} GB/s; layer from host ELTs {host_build_ms:.3f} ms")
     # the step's table is bitwise the one built from the host ELTs
     y2 = A.run_layer(yet, lay)
@@ -623,6 +664,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_synchronous": ms_sync,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
