@@ -256,29 +256,6 @@ void set_terms(ara::LayerHost &h, int32_t n_elts, const double *h_ret, const dou
     h.t64.n_elts = h.t32.n_elts = n_elts;
 }
 
-// LDS filters of the fused pass: a block filter of n_fwords words (blocks of
-// 2^fshift events) and, when blocks hold more than one event, a hashed filter
-// of n_hwords words (a power of two) in the LDS the block filter leaves free.
-void filter_geometry(int32_t C, int32_t &fshift, int32_t &n_fwords, int32_t &n_hwords, int32_t &hshift) {
-    fshift = 0;
-    while ((((int64_t)C + (1LL << fshift) - 1) >> fshift) > ara::kFilterBits) ++fshift;
-    const int64_t n_blocks = ((int64_t)C + (1LL << fshift) - 1) >> fshift;
-    n_fwords = (int32_t)((n_blocks + 31) / 32);
-    n_hwords = 0;
-    hshift = 0;
-    const int64_t room = ara::kFusedLdsBytes / 4 - n_fwords;
-    if (fshift > 0 && room >= 1) {
-        int64_t w = 1;
-        int log2_bits = 5;
-        while (w * 2 <= room) {
-            w *= 2;
-            ++log2_bits;
-        }
-        n_hwords = (int32_t)w;
-        hshift = 32 - log2_bits;
-    }
-}
-
 template <typename T>
 ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *loss, const std::vector<int64_t> &start,
                         const int64_t *sizes) {
@@ -332,7 +309,7 @@ ara_status build_tables(ara::LayerHost &h, const int32_t *ids, const double *los
         if (e != hipSuccess) return hip_fail(e, "current device");
         if (dev < 0 || dev >= ara::kMaxDevices) return fail(ARA_ERR_UNSUPPORTED, "device id beyond the library's tables");
         int32_t fshift = 0, n_fwords = 0, n_hwords = 0, hshift = 0;
-        filter_geometry((int32_t)C, fshift, n_fwords, n_hwords, hshift);
+        ara::filter_geometry((int32_t)C, fshift, n_fwords, n_hwords, hshift);
         void *d_occ = nullptr, *d_filt = nullptr;
         // catalogue + 1 entries: occ[C] stays 0 for the pass's unmarked lanes
         e = dev_alloc(&d_occ, ((size_t)C + 1) * sizeof(T));
@@ -554,7 +531,7 @@ ara_status ara_create_layer(ara_yet yet, int32_t n_elts, const int32_t *h_elt_id
     // a fused layer built on the GPU has its entries checked by the build's
     // kernels; every other layer checks them here
     int32_t fshift = 0, n_fwords = 0, n_hwords = 0, hshift = 0;
-    filter_geometry(C, fshift, n_fwords, n_hwords, hshift);
+    ara::filter_geometry(C, fshift, n_fwords, n_hwords, hshift);
     const bool fused = layout == ARA_LAYOUT_AUTO || layout == ARA_LAYOUT_FUSED;
     const bool gpu_checked = fused && ara::fused_build_fits(C, fshift, start[n_elts]);
     if (!gpu_checked) {
@@ -698,7 +675,7 @@ ara_status ara_create_pool(ara_yet yet, int32_t n_elts, const int32_t *h_elt_ids
     p->max_layers = max_layers;
     p->off = start;
     (void)hipGetDevice(&p->device);
-    filter_geometry(yet->catalog, p->fshift, p->n_fwords, p->n_hwords, p->hshift);
+    ara::filter_geometry(yet->catalog, p->fshift, p->n_fwords, p->n_hwords, p->hshift);
     const size_t total = (size_t)start[n_elts];
     hipStream_t s = ara::internal_stream();
     hipError_t e = dev_alloc(&p->d_ids, total * sizeof(int32_t));
@@ -1061,7 +1038,7 @@ ara_status ara_create_batch(ara_yet yet, const ara_layer *layers, int32_t n_laye
     b->precision = prec;
     b->catalog = yet->catalog;
     (void)hipGetDevice(&b->device);
-    filter_geometry(yet->catalog, b->fshift, b->n_fwords, b->n_hwords, b->hshift);
+    ara::filter_geometry(yet->catalog, b->fshift, b->n_fwords, b->n_hwords, b->hshift);
     hipError_t e = hipEventCreateWithFlags(&b->last_run, hipEventDisableTiming);
     if (e != hipSuccess) b->last_run = nullptr;
     if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void **>(&b->d_ylts), sizeof(double *) * ARA_MAX_BATCH);

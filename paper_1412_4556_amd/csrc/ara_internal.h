@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/ara.h"
+#include "ara_index.h"
 
 namespace ara {
 
@@ -75,6 +76,29 @@ constexpr int64_t kFilterBits = 1 << 20;
 // products' top bits vary slowly over IDs below 2^21: twice the false hits).
 constexpr int64_t kFusedLdsBytes = 160 * 1024;
 constexpr uint32_t kHashMul24 = 0xEBCA6Bu;
+
+// LDS filters of the fused pass: a block filter of n_fwords words (blocks of
+// 2^fshift events) and, when blocks hold more than one event, a hashed filter
+// of n_hwords words (a power of two) in the LDS the block filter leaves free.
+inline void filter_geometry(int32_t C, int32_t &fshift, int32_t &n_fwords, int32_t &n_hwords, int32_t &hshift) {
+    fshift = 0;
+    while ((((int64_t)C + (1LL << fshift) - 1) >> fshift) > kFilterBits) ++fshift;
+    const int64_t n_blocks = ((int64_t)C + (1LL << fshift) - 1) >> fshift;
+    n_fwords = (int32_t)((n_blocks + 31) / 32);
+    n_hwords = 0;
+    hshift = 0;
+    const int64_t room = kFusedLdsBytes / 4 - n_fwords;
+    if (fshift > 0 && room >= 1) {
+        int64_t w = 1;
+        int log2_bits = 5;
+        while (w * 2 <= room) {
+            w *= 2;
+            ++log2_bits;
+        }
+        n_hwords = (int32_t)w;
+        hshift = 32 - log2_bits;
+    }
+}
 
 enum Layout : int32_t {
     kDirect = ARA_LAYOUT_DIRECT,
@@ -208,13 +232,9 @@ hipError_t launch_pool_layer(LayerHost &L, const int32_t *d_ids, const void *d_l
 // 2 duplicate ID in one ELT, 4 bad loss; cleared by the caller); else
 // d_loss holds the pool's values (the layer's precision) and d_flags is
 // unused.  Returns hipErrorNotSupported when the layer does not fit.
-constexpr int kBuildRange = 8192;
-constexpr int kBuildThreads = 1024;
+// (kBuildRange, kBuildThreads, kBuildList and the build's index arithmetic:
+// ara_index.h)
 constexpr int kBuildUnroll = 16;
-// Entries of a range the build lists before adding them (a range with more
-// reads every ID of the layer instead, taking the ELTs one at a time); a
-// multiple of kBuildThreads.
-constexpr int kBuildList = 4 * kBuildThreads;
 // IDs read over all work-groups if every range overflowed its list
 constexpr int64_t kBuildReadBudget = (int64_t)1 << 30;
 struct BuildSegs {

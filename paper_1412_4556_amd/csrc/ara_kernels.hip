@@ -1695,22 +1695,11 @@ __device__ __forceinline__ void build_chunk_ids(const int32_t *__restrict__ ids,
     }
 }
 
-// Where the build keeps a range's entry list until it adds them: range g
-// (catalogue events [g R, g R + n_g), R = kBuildRange) lists its entries in
-// its own part of the table, occ[g R ..], which is written only once the list
-// has been read, and counts them in the first block-filter word of the range,
-// written only by the range's own work-group once it has read the count.
+// Range g's entry list, in range g's part of the table (range_capacity
+// entries of 8 bytes).
 template <typename T>
 __device__ __forceinline__ uint64_t *range_list(T *occ, int64_t g) {
     return reinterpret_cast<uint64_t *>(occ + g * kBuildRange);
-}
-
-template <typename T>
-__device__ __forceinline__ int range_capacity(int64_t g, int32_t catalog) {
-    const int64_t left = (int64_t)catalog + 1 - g * kBuildRange;
-    const int64_t n = left < kBuildRange ? left : kBuildRange;
-    const int64_t cap = n * (int64_t)sizeof(T) / (int64_t)sizeof(uint64_t);
-    return cap < kBuildList ? (int)cap : kBuildList;
 }
 
 // The entry lists of a layer's ranges: one work-group per kListChunk entries
@@ -1726,19 +1715,17 @@ __device__ __forceinline__ int range_capacity(int64_t g, int32_t catalog) {
 constexpr int kListThreads = 256;
 constexpr int kListPerThread = 8;
 constexpr int kListChunk = kListThreads * kListPerThread;
-constexpr int kListHist = 4096;
 template <typename T, bool CHECK>
 __global__ __launch_bounds__(kListThreads) void k_build_lists(const int32_t *__restrict__ ids, BuildSegs sg,
                                                               int32_t catalog, T *__restrict__ occ,
-                                                              uint32_t *__restrict__ filt, int32_t range_words,
+                                                              uint32_t *__restrict__ filt, int32_t fshift,
                                                               int *flags) {
-    static_assert(kBuildRange == (1 << 13), "an event's range is its ID >> 13");
     __shared__ int hist[kListHist];
     const int j = blockIdx.y;
     const int64_t m = sg.count[j];
     const int64_t i0 = (int64_t)blockIdx.x * kListChunk;
     if (i0 >= m) return;  // uniform: the work-group has no entries
-    const int n_ranges = (int)(((int64_t)catalog + kBuildRange) >> 13);
+    const int n_ranges = (int)build_ranges(catalog);
     const bool local = n_ranges <= kListHist;
     if (local) {
         for (int k = threadIdx.x; k < n_ranges; k += blockDim.x) hist[k] = 0;
@@ -1764,25 +1751,25 @@ __global__ __launch_bounds__(kListThreads) void k_build_lists(const int32_t *__r
             e[u] = -1;
             continue;
         }
-        const int g = e[u] >> 13;
-        place[u] = local ? atomicAdd(&hist[g], 1) : atomicAdd(&filt[(int64_t)g * range_words], 1u);
+        const int64_t g = build_range_of(e[u]);
+        place[u] = local ? atomicAdd(&hist[g], 1) : atomicAdd(&filt[range_count_word(g, fshift)], 1u);
     }
     if (local) {
         __syncthreads();
         // each range's share of the list, from its count
         for (int k = threadIdx.x; k < n_ranges; k += blockDim.x) {
             const int c = hist[k];
-            if (c) hist[k] = (int)atomicAdd(&filt[(int64_t)k * range_words], (uint32_t)c);
+            if (c) hist[k] = (int)atomicAdd(&filt[range_count_word(k, fshift)], (uint32_t)c);
         }
         __syncthreads();
     }
 #pragma unroll
     for (int u = 0; u < kListPerThread; ++u) {
         if (place[u] < 0) continue;
-        const int g = e[u] >> 13;
+        const int64_t g = build_range_of(e[u]);
         const int at = place[u] + (local ? hist[g] : 0);
-        if (at < range_capacity<T>(g, catalog)) {
-            const uint32_t off = (uint32_t)e[u] & (kBuildRange - 1);
+        if (at < range_capacity(g, catalog, (int)sizeof(T))) {
+            const uint32_t off = build_range_offset(e[u]);
             const int64_t pos = sg.begin[j] + i0 + u * kListThreads + threadIdx.x;
             range_list(occ, g)[at] = ((uint64_t)j << 53) | ((uint64_t)off << 40) | (uint64_t)pos;
         }
@@ -1827,13 +1814,12 @@ __global__ __launch_bounds__(kBuildThreads) void k_fused_build(const int32_t *__
     int *stamp = reinterpret_cast<int *>(lo + (sizeof(T) == sizeof(float) ? kBuildRange : 0));  // CHECK
     const int64_t g = blockIdx.x;
     const int64_t base = g * kBuildRange;
-    const int64_t top = base + kBuildRange < (int64_t)catalog + 1 ? base + kBuildRange : (int64_t)catalog + 1;
-    const uint32_t nloc = (uint32_t)(top - base);
+    const uint32_t nloc = (uint32_t)range_events(g, catalog);
     const int wshift = 5 + fshift;
-    const int64_t w0 = base >> wshift;
+    const int64_t w0 = range_count_word(g, fshift);
     // the count (a range past the last filter word holds only the zero slot)
     const int n_list = w0 < n_fwords ? (int)filt[w0] : 0;
-    const bool listed = n_list <= range_capacity<T>(g, catalog);
+    const bool listed = n_list <= range_capacity(g, catalog, (int)sizeof(T));
     uint64_t le[kPerThread];
     LT lv[kPerThread];
     if (listed) {
@@ -2221,8 +2207,8 @@ const Terms<float> &terms_of<float>(const LayerHost &L) {
 }  // namespace
 
 bool fused_build_fits(int64_t catalog, int32_t fshift, int64_t n_entries) {
-    if ((kBuildRange >> (5 + fshift)) < 1 || ((kBuildRange >> (5 + fshift)) << (5 + fshift)) != kBuildRange) return false;
-    const int64_t groups = (catalog + 1 + kBuildRange - 1) / kBuildRange;
+    if (!build_ranges_cover_words(fshift)) return false;
+    const int64_t groups = build_ranges((int32_t)catalog);
     // a work-group whose range overflows its list reads every ID of the layer
     return groups * (n_entries > 0 ? n_entries : 1) <= kBuildReadBudget;
 }
@@ -2254,11 +2240,10 @@ hipError_t fused_build_t(LayerHost &L, const int32_t *d_ids, const void *d_loss,
                        (int64_t)(L.tab.n_fwords + L.tab.n_hwords));
     int64_t longest = 0;
     for (int j = 0; j < n; ++j) longest = sg.count[j] > longest ? sg.count[j] : longest;
-    const int range_words = kBuildRange >> (5 + L.tab.fshift);
     if (longest > 0)
         hipLaunchKernelGGL((k_build_lists<T, CHECK>), dim3((unsigned)((longest + kListChunk - 1) / kListChunk), (unsigned)n),
-                           dim3(kListThreads), 0, s, d_ids, sg, L.catalog, occ, filt, range_words, d_flags);
-    const int64_t groups = ((int64_t)L.catalog + 1 + kBuildRange - 1) / kBuildRange;
+                           dim3(kListThreads), 0, s, d_ids, sg, L.catalog, occ, filt, L.tab.fshift, d_flags);
+    const int64_t groups = build_ranges(L.catalog);
     hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kBuildThreads), lds, s, d_ids, static_cast<const LT *>(d_loss),
                        sg, L.catalog, t.occ_ret, t.occ_lim, occ, filt, L.tab.n_fwords, L.tab.fshift,
                        filt + L.tab.n_fwords, L.tab.n_hwords, L.tab.hshift, d_flags);

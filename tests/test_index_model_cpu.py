@@ -1,9 +1,13 @@
-"""The YET load indexing of the fused and batched passes, checked on the CPU:
-tests/index_model.cpp runs the index functions the kernels call
-(paper_1412_4556_amd/csrc/ara_index.h) over trials of every length 0..1001 at
-every start modulo 4, and fixed-length YETs, and checks that every 16-byte
-load stays within the YET's last granule, that the clamp never moves a load
-holding trial elements, and that each event is taken exactly once."""
+"""The kernels' index arithmetic, checked on the CPU: tests/index_model.cpp
+runs the index functions the kernels call
+(paper_1412_4556_amd/csrc/ara_index.h).  YET loads of the fused and batched
+passes, over trials of every length 0..1001 at every start modulo 4 and
+fixed-length YETs: every 16-byte load stays within the YET's last granule,
+the clamp never moves a load holding trial elements, and each event is taken
+exactly once.  The fused table build, over catalogue sizes from 1 to
+2^31 - 1: every event's range and offset give back the event, each range's
+count sits in its own block-filter word inside the filter, and each range's
+entry list stays inside the range's part of the table."""
 import os
 import shutil
 import subprocess
