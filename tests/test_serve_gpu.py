@@ -64,6 +64,35 @@ def test_pool_layer_equals_host_layer(prec):
     assert P.free_slots == 4
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_pool_layer_repeated_and_empty_elts(prec):
+    """A pool layer may name one pool ELT several times and may hold an
+    empty ELT: its table gives bitwise the YLT of the host-built layer with
+    the same ELT list, within tolerance of the oracle."""
+    ids, off, pool = _setup(T=1500)
+    T, C = len(off) - 1, 30000
+    e_ids = list(pool.ids) + [np.zeros(0, np.int32)]
+    e_loss = list(pool.losses) + [np.zeros(0)]
+    empty = len(e_ids) - 1
+    yet = A.yet_from_numpy(ids, off, T, C)
+    P = A.Pool(yet, e_ids, e_loss, prec, max_layers=2)
+    pick = np.array([3, 7, 3, empty, 7, 0], np.int32)
+    ret = np.array([pool.ret[i] if i != empty else 0.0 for i in pick])
+    lim = np.array([pool.lim[i] if i != empty else np.inf for i in pick])
+    terms = (50.0, 1e6, 100.0, 1e8)
+    spec = W.LayerSpec([e_ids[i] for i in pick], [e_loss[i] for i in pick], ret, lim, *terms)
+    lp = P.layer(pick, ret, lim, *terms)
+    y_p = A.run_layer(yet, lp).cpu().numpy()
+    lh = A.Layer(yet, spec, prec, "fused")
+    y_h = A.run_layer(yet, lh).cpu().numpy()
+    assert np.array_equal(y_p, y_h)
+    assert (y_p > 0).mean() > 0.05
+    assert_close_to_oracle(y_p, oracle_run(ids, off, T, C, 0, spec), prec)
+    lp.close()
+    lh.close()
+    assert P.free_slots == 2
+
+
 def test_pool_admission_limit():
     ids, off, pool = _setup(T=500)
     yet = A.yet_from_numpy(ids, off, 500, 30000)
