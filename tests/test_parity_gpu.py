@@ -580,3 +580,38 @@ def test_fused_build_more_ranges_than_list_counters(prec):
     with pytest.raises(L.AraError) as ei:
         A.Layer(yet, W.LayerSpec(bad_ids, elos, ret, lim, 500.0, 1e6, 1e4, 1e8), prec, "fused")
     assert ei.value.name == "ARA_ERR_DUP_EVENT"
+
+
+@pytest.mark.parametrize("C", [8191, 8192, 8193, 16384, 24577])
+def test_fused_build_range_boundaries(C):
+    """Catalogues around multiples of the build's 8,192-event ranges (the
+    last range holding only the zero slot when the catalogue is a multiple,
+    a single event past a multiple): the GPU-built table gives bitwise the
+    compact layout's YLT, from host ELTs and from a device pool, in both
+    precisions, with events at both ends of every range."""
+    rng = np.random.default_rng(C)
+    edges = np.array([e for g in range(0, C, 8192) for e in (g, g + 1, g + 8191) if e < C] + [C - 1], np.int64)
+    eids = []
+    for j in range(3):
+        rest = rng.choice(C, size=min(C // 3, 3000), replace=False)
+        eids.append(np.unique(np.concatenate([edges, rest])).astype(np.int32))
+    elos = [rng.lognormal(8.0, 1.5, len(e)) for e in eids]
+    ret = np.array([np.quantile(l, 0.1) for l in elos])
+    lim = np.array([np.quantile(l, 0.95) for l in elos])
+    spec = W.LayerSpec(eids, elos, ret, lim, 100.0, 1e6, 1e3, 1e8)
+    T = 400
+    lens = rng.poisson(50, T)
+    off = np.zeros(T + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    ids = np.where(rng.random(off[-1]) < 0.3, rng.choice(edges, off[-1]), rng.integers(0, C, off[-1])).astype(np.int32)
+    yet = A.yet_from_numpy(ids, off, T, C)
+    ref = oracle_run(ids, off, T, C, 0, spec)
+    for prec in PRECS:
+        yf = A.run_layer(yet, A.Layer(yet, spec, prec, "fused")).cpu().numpy()
+        yc = A.run_layer(yet, A.Layer(yet, spec, prec, "compact")).cpu().numpy()
+        assert np.array_equal(yf, yc), prec
+        P = A.Pool(yet, eids, elos, prec, max_layers=1)
+        lp = P.layer(np.arange(3, dtype=np.int32), ret, lim, 100.0, 1e6, 1e3, 1e8)
+        assert np.array_equal(A.run_layer(yet, lp).cpu().numpy(), yf), prec
+        lp.close()
+        assert_close_to_oracle(yf, ref, prec)
