@@ -432,6 +432,10 @@ __global__ __launch_bounds__(256) void k_trial_pass_events(YetView y, TablesView
 // flight.  Each lane still adds its events in the order of k_trial_pass (chunk
 // by chunk, four consecutive events per chunk) and skipped events would add
 // exactly zero, so the YLT is bitwise the one of the other layouts.
+// kGroup is a build-time choice (-DARA_FUSED_GROUP=2|4|8, the same YLT
+// bits): on MI355X four chunks are the fastest for fixed-length and ragged
+// YETs in both precisions (two: 7 % and 25 % slower; eight: the fixed-length
+// pass spills at the 128 VGPRs of 1024-thread groups and takes twice as long).
 #ifndef ARA_FUSED_GROUP
 #define ARA_FUSED_GROUP 4
 #endif
@@ -1976,26 +1980,26 @@ hipError_t launch_pass_t(const YetView &y, const LayerHost &L, const Terms<T> &t
         using EventsK = void (*)(YetView, const int64_t *, FusedFilter, int32_t, const T *, double, double, double *,
                                  double *, double *);
 #define ARA_FUSED_PASSES(O32)                                                                                      \
-    &k_trial_pass_fused<T, true, true, false, 4, false, O32>, &k_trial_pass_fused<T, false, true, false, 4, false, O32>, \
-        &k_trial_pass_fused<T, false, false, false, 4, false, O32>,                                                    \
-        &k_trial_pass_fused<T, true, true, true, 4, false, O32>, &k_trial_pass_fused<T, false, true, true, 4, false, O32>, \
-        &k_trial_pass_fused<T, false, false, true, 4, false, O32>,                                                     \
-        &k_trial_pass_fused<T, true, true, false, 4, true, O32>, &k_trial_pass_fused<T, false, true, false, 4, true, O32>, \
-        &k_trial_pass_fused<T, false, false, false, 4, true, O32>,                                                     \
-        &k_trial_pass_fused<T, true, true, true, 4, true, O32>, &k_trial_pass_fused<T, false, true, true, 4, true, O32>,   \
-        &k_trial_pass_fused<T, false, false, true, 4, true, O32>
+    &k_trial_pass_fused<T, true, true, false, kGroup, false, O32>, &k_trial_pass_fused<T, false, true, false, kGroup, false, O32>, \
+        &k_trial_pass_fused<T, false, false, false, kGroup, false, O32>,                                                    \
+        &k_trial_pass_fused<T, true, true, true, kGroup, false, O32>, &k_trial_pass_fused<T, false, true, true, kGroup, false, O32>, \
+        &k_trial_pass_fused<T, false, false, true, kGroup, false, O32>,                                                     \
+        &k_trial_pass_fused<T, true, true, false, kGroup, true, O32>, &k_trial_pass_fused<T, false, true, false, kGroup, true, O32>, \
+        &k_trial_pass_fused<T, false, false, false, kGroup, true, O32>,                                                     \
+        &k_trial_pass_fused<T, true, true, true, kGroup, true, O32>, &k_trial_pass_fused<T, false, true, true, kGroup, true, O32>,   \
+        &k_trial_pass_fused<T, false, false, true, kGroup, true, O32>
         const PassK pk[24] = {ARA_FUSED_PASSES(false), ARA_FUSED_PASSES(true)};
 #undef ARA_FUSED_PASSES
         // 32-bit table offsets while every byte of the table (zero slot
         // included) lies below 2^32
         const bool off32 = ((int64_t)L.catalog + 1) * (int64_t)sizeof(T) <= (1LL << 32);
         const int pv = variant + (d_omax ? 6 : 0) + (off32 ? 12 : 0);
-        const EventsK ek[6] = {&k_trial_pass_events_fused<T, true, true, false, 4>,
-                               &k_trial_pass_events_fused<T, false, true, false, 4>,
-                               &k_trial_pass_events_fused<T, false, false, false, 4>,
-                               &k_trial_pass_events_fused<T, true, true, true, 4>,
-                               &k_trial_pass_events_fused<T, false, true, true, 4>,
-                               &k_trial_pass_events_fused<T, false, false, true, 4>};
+        const EventsK ek[6] = {&k_trial_pass_events_fused<T, true, true, false, kGroup>,
+                               &k_trial_pass_events_fused<T, false, true, false, kGroup>,
+                               &k_trial_pass_events_fused<T, false, false, false, kGroup>,
+                               &k_trial_pass_events_fused<T, true, true, true, kGroup>,
+                               &k_trial_pass_events_fused<T, false, true, true, kGroup>,
+                               &k_trial_pass_events_fused<T, false, false, true, kGroup>};
         const void *kern = events ? reinterpret_cast<const void *>(ek[variant]) : reinterpret_cast<const void *>(pk[pv]);
         hipError_t ae = allow_dynamic_lds(kern, (int)kFusedLdsBytes);
         if (ae != hipSuccess) return ae;
