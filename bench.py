@@ -11,7 +11,9 @@ One step = the layer's fused table built on the GPU from its 16 ELTs, which
 are resident in HBM (steps 1-3 of the method for every catalogue event: the
 per-ELT terms, the sum over the ELTs, the occurrence terms), the trial pass
 over every trial (the cumulative sum and the aggregate terms, YLT written to
-HBM), and PML/TVaR at 1-in-100 and 1-in-250 returned to the host.  Prints one
+HBM), and PML/TVaR at 1-in-100 and 1-in-250 returned to the host.  The timed
+steps are pipelined: step i + 1 is queued before step i's PML/TVaR is read on
+the host (the line also gives the time per step one at a time).  Prints one
 JSON line on stdout; progress goes to stderr.
 """
 import argparse
