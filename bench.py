@@ -546,10 +546,14 @@ def main():
     ylt_host = ylt.cpu().numpy()  # the timed steps' YLT, for the parity check against the oracle
     # the same layer built from host ELTs (upload over PCIe, checks, table),
     # outside the step; the second build is the steady-state cost
-    A.Layer(yet, spec, args.precision, "fused").close()
+    # (from the ELTs as the C ABI takes them, every ELT's entries back to
+    # back in host memory; joining the spec's per-ELT arrays is not timed)
+    flat = spec.concat()
+    terms = (spec.ret, spec.lim, spec.occ_ret, spec.occ_lim, spec.agg_ret, spec.agg_lim)
+    A.Layer.from_flat(yet, *flat, *terms, args.precision, "fused").close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lay = A.Layer(yet, spec, args.precision, "fused")
+    lay = A.Layer.from_flat(yet, *flat, *terms, args.precision, "fused", spec=spec)
     torch.cuda.synchronize()
     host_build_ms = (time.perf_counter() - t0) * 1e3
     log(f"layer: {J} ELTs, layout {lay.layout}, precision {lay.precision}, {lay.device_bytes} device bytes")

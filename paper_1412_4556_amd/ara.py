@@ -76,16 +76,31 @@ class Layer:
 
     def __init__(self, yet: Yet, spec, precision: str = "fp64", layout: str = "auto"):
         ids, losses, sizes = spec.concat()
+        self._create(yet, ids, losses, sizes, spec.ret, spec.lim, spec.occ_ret, spec.occ_lim, spec.agg_ret,
+                     spec.agg_lim, precision, layout)
+        self.spec = spec
+
+    @classmethod
+    def from_flat(cls, yet: Yet, ids, losses, sizes, ret, lim, occ_ret, occ_lim, agg_ret, agg_lim,
+                  precision: str = "fp64", layout: str = "auto", spec=None) -> "Layer":
+        """The layer from its ELTs as ara_create_layer takes them: every ELT's
+        IDs and losses back to back (ELT j: sizes[j] entries, in layer order)."""
+        obj = cls.__new__(cls)
+        obj._create(yet, ids, losses, sizes, ret, lim, occ_ret, occ_lim, agg_ret, agg_lim, precision, layout)
+        obj.spec = spec
+        return obj
+
+    def _create(self, yet, ids, losses, sizes, ret, lim, occ_ret, occ_lim, agg_ret, agg_lim, precision, layout):
         ids, losses, sizes = _np(ids, np.int32), _np(losses, np.float64), _np(sizes, np.int64)
-        ret, lim = _np(spec.ret, np.float64), _np(spec.lim, np.float64)
+        ret, lim = _np(ret, np.float64), _np(lim, np.float64)
+        if len(ret) != len(sizes) or len(lim) != len(sizes):
+            raise ValueError("one retention and one limit per ELT")
         h = ctypes.c_void_p()
-        L.check(L.lib().ara_create_layer(yet.handle, int(spec.n_elts), _vp(ids), _vp(losses), _vp(sizes), _vp(ret),
-                                         _vp(lim), float(spec.occ_ret), float(spec.occ_lim), float(spec.agg_ret),
-                                         float(spec.agg_lim), PRECISIONS[precision], LAYOUTS[layout],
-                                         ctypes.byref(h)))
+        L.check(L.lib().ara_create_layer(yet.handle, int(len(sizes)), _vp(ids), _vp(losses), _vp(sizes), _vp(ret),
+                                         _vp(lim), float(occ_ret), float(occ_lim), float(agg_ret), float(agg_lim),
+                                         PRECISIONS[precision], LAYOUTS[layout], ctypes.byref(h)))
         self._h = h
         self.yet = yet
-        self.spec = spec
 
     @classmethod
     def _wrap(cls, handle, yet, spec):

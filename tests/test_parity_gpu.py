@@ -615,3 +615,19 @@ def test_fused_build_range_boundaries(C):
         assert np.array_equal(A.run_layer(yet, lp).cpu().numpy(), yf), prec
         lp.close()
         assert_close_to_oracle(yf, ref, prec)
+
+
+def test_layer_from_flat_arrays():
+    """The binding's flat-array constructor (the ELTs as ara_create_layer
+    takes them) builds the same layer as the per-ELT spec, and rejects terms
+    that do not match the ELT count."""
+    ids, off, spec = W.random_case(77, 300, 40.0, 5000, 3, 600)
+    T = len(off) - 1
+    yet = A.yet_from_numpy(ids, off, T, 5000)
+    terms = (spec.ret, spec.lim, spec.occ_ret, spec.occ_lim, spec.agg_ret, spec.agg_lim)
+    for prec in PRECS:
+        a = A.run_layer(yet, A.Layer(yet, spec, prec, "fused")).cpu().numpy()
+        b = A.run_layer(yet, A.Layer.from_flat(yet, *spec.concat(), *terms, prec, "fused")).cpu().numpy()
+        assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        A.Layer.from_flat(yet, *spec.concat(), spec.ret[:2], spec.lim, *terms[2:])
