@@ -87,6 +87,7 @@ struct ara_batch_s {
     int dgroup[3] = {0, 0, 0};
     bool tuned = false;
     bool use_graph = true;
+    int capture_failures = 0;  // in a row; the batch stops capturing after kMaxCaptureFailures
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     // what the captured graph's kernel arguments hold: it is replayed only
@@ -138,6 +139,17 @@ long long fault_budget() {
     return v;
 }
 std::atomic<long long> g_alloc_count{0};
+
+// Optional capture-failure injection for tests of the fallback:
+// ARA_FAULT_CAPTURE=1 makes every batch graph capture fail as an
+// invalidated capture does.
+bool fault_capture() {
+    static bool v = [] {
+        const char *s = std::getenv("ARA_FAULT_CAPTURE");
+        return s && std::atoi(s) != 0;
+    }();
+    return v;
+}
 
 // Device staging of the ELTs of fused layers built from host memory: one
 // buffer per device, grown on demand and kept until the process ends, used
@@ -1237,7 +1249,10 @@ hipError_t tune_dense(ara_batch b, hipStream_t s) {
     return hipSuccess;
 }
 
+constexpr int kMaxCaptureFailures = 3;
+
 hipError_t capture_batch(ara_batch b) {
+    if (fault_capture()) return hipErrorStreamCaptureInvalidated;
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
@@ -1290,7 +1305,20 @@ ara_status launch_batch(ara_batch batch, hipStream_t s) {
         if (batch->exec && !graph_current(batch)) drop_graph(batch);
         if (!batch->exec) {
             e = capture_batch(batch);
-            if (e != hipSuccess) return hip_fail(e, "batch graph capture");
+            if (e != hipSuccess) {
+                // A capture can fail for reasons outside the batch: the HIP
+                // runtime invalidates it when another host thread makes a
+                // synchronizing call (a free, an allocation) meanwhile.  The
+                // pass then runs as a direct launch, the same kernels with the
+                // same arguments, and the next run captures again; after
+                // kMaxCaptureFailures failures in a row the batch stops trying.
+                (void)hipGetLastError();
+                if (++batch->capture_failures >= kMaxCaptureFailures) batch->use_graph = false;
+                e = pass_once(batch, s);
+                if (e != hipSuccess) return hip_fail(e, "batch launch after a failed graph capture");
+                return ARA_OK;
+            }
+            batch->capture_failures = 0;
         }
         e = hipGraphLaunch(batch->exec, s);
         if (e != hipSuccess) return hip_fail(e, "batch graph launch");
