@@ -198,9 +198,9 @@ ara_status ara_run_layer_max_occurrence(ara_yet yet, ara_layer layer, double *d_
  * and the number of 256-event chunks loaded per step) is chosen on the first
  * run by timing candidates (and remembered per precision, power-of-two layer
  * count or record width, and YET), then the pass is replayed from a HIP
- * graph captured once.  A capture that fails (the HIP runtime invalidates a
- * capture when another host thread makes a synchronizing call meanwhile)
- * costs nothing but the graph: that run launches the pass directly, the next
+ * graph captured once.  A capture that fails (a capture can be invalidated
+ * from outside, e.g. by a synchronizing call another host thread makes
+ * meanwhile) costs nothing but the graph: that run launches the pass directly, the next
  * run captures again, and after three failures in a row the batch launches
  * directly from then on.
  * Asynchronous on hip_stream. */

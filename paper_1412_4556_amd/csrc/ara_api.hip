@@ -1306,10 +1306,10 @@ ara_status launch_batch(ara_batch batch, hipStream_t s) {
         if (!batch->exec) {
             e = capture_batch(batch);
             if (e != hipSuccess) {
-                // A capture can fail for reasons outside the batch: the HIP
-                // runtime invalidates it when another host thread makes a
-                // synchronizing call (a free, an allocation) meanwhile.  The
-                // pass then runs as a direct launch, the same kernels with the
+                // A capture can fail for reasons outside the batch (it can be
+                // invalidated from outside, e.g. by a synchronizing call --
+                // a free, an allocation -- that another host thread makes
+                // meanwhile).  The pass then runs as a direct launch, the same kernels with the
                 // same arguments, and the next run captures again; after
                 // kMaxCaptureFailures failures in a row the batch stops trying.
                 (void)hipGetLastError();
