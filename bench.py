@@ -65,8 +65,8 @@ def cpu_model():
 
 def host_cpus():
     """What the host offers this process: logical CPUs, the CPUs it may run
-    on, and the thread count the machine sets for OpenMP (on a GPU machine of
-    this pool: the CPU share of one GPU)."""
+    on, and the thread count the machine sets for OpenMP (on a host shared
+    by several GPUs: the CPU share of one GPU)."""
     try:
         aff = len(os.sched_getaffinity(0))
     except Exception:
@@ -78,7 +78,7 @@ def host_cpus():
 
 def host_threads():
     """Threads of the CPU baseline: every CPU this process may run on, capped
-    by OMP_NUM_THREADS when the machine sets it (the machine's CPU share)."""
+    by OMP_NUM_THREADS when the machine sets it (a GPU's share of the host)."""
     info = host_cpus()
     n = info["affinity_cpus"]
     if info["omp_num_threads"]:
@@ -268,7 +268,7 @@ def cpu_baseline(wl, spec, target_s, gpu_ylt=None, gpu_pml_tvar=None, rps=(), gp
            "cpu_model": cpus["cpu_model"], "seconds": dt,
            "host": {**cpus, "threads_used": threads,
                     "threads_rule": "every CPU of the process's affinity, capped by OMP_NUM_THREADS when set "
-                                    "(the CPU share of one GPU on the GPU box)"}}
+                                    "(the CPU share of one GPU on a shared host)"}}
     # the same loop on one core (the paper's sequential form), on a smaller sample
     n1 = int(min(wl.yet.n_trials, max(100, n / threads / 4)))
     dt1, ev1, _ = run(n1, 1)
